@@ -1,0 +1,292 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests reuses the oracle's own code to produce an expected value:
+expectations come from the paper's printed worked examples (tests/golden/),
+closed forms, brute force written here independently (Python's stable
+`sorted`), invariants, or library routines (numpy.sort) in the cases where the
+definition reduces to them.
+"""
+import itertools
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import read_golden
+
+
+def field(k, begin, end):
+    return (int(k) >> begin) & ((1 << (end - begin)) - 1)
+
+
+def brute_sort(keys, vals, begin, end):
+    """Stable comparison sort by the bit field [begin, end): Python's sorted is stable."""
+    order = sorted(range(len(keys)), key=lambda i: field(keys[i], begin, end))
+    ko = np.array([keys[i] for i in order], dtype=keys.dtype)
+    vo = None if vals is None else np.array([vals[i] for i in order], dtype=np.uint32)
+    return ko, vo
+
+
+# --------------------------------------------------------------- paper examples
+
+def test_prefix_sum_worked_example():
+    """Section 2: exclusive sum of <8,6,7,5,3,0,9,2> is <0,8,14,21,26,29,29,38>."""
+    g = read_golden("prefix_sum_example.txt")
+    hist = np.array([g["histogram"]], dtype=np.uint64)
+    assert hist.shape[1] == g["radix"][0]
+    off = oracle.exclusive_sums(hist)
+    assert off[0].tolist() == g["offsets"]
+
+
+def test_digit_flags_worked_example():
+    """Section 2: keys <17,8,24,5>, low 3-bit place, flags and flag prefix for digit 0."""
+    g = read_golden("digit_flags_example.txt")
+    keys = np.array(g["keys"], dtype=np.uint32)
+    d = g["digit_bits"][0]
+    digits = [oracle.digit(k, 0, 32, d, 0) for k in keys]
+    flags = [1 if x == g["digit"][0] else 0 for x in digits]
+    assert flags == g["flags"]
+    # The exclusive prefix of the flags, computed by the oracle's scan.
+    pref = oracle.exclusive_sums(np.array([flags], dtype=np.uint64))[0].tolist()
+    assert pref == g["flag_prefix"]
+    # In one binning iteration each flagged key lands at bin start + its prefix.
+    hist = oracle.histograms(keys, 0, d, d)
+    off = oracle.exclusive_sums(hist)
+    out, _ = oracle.binning_pass(keys, 0, d, off[0])
+    base = int(off[0][g["digit"][0]])
+    for i, f in enumerate(flags):
+        if f:
+            assert out[base + g["flag_prefix"][i]] == keys[i]
+
+
+def test_lookback_figure7():
+    """Figure 7: local counts -> inclusive prefixes 11, 26, 35, 45, 53."""
+    g = read_golden("lookback_fig7.txt")
+    incl = oracle.inclusive_scan(g["local_counts"]).tolist()
+    assert incl == g["inclusive"]
+    assert incl[3] == g["exclusive_of_tile_4"][0]
+
+
+def test_lookback_figure7_status_words():
+    """The final chained-scan state of Figure 7f through the status-word oracle.
+
+    Five tiles of 16 keys each; tile t holds local_counts[t] keys whose 4-bit
+    digit is 0 and the rest with digit 1. Every counter of digit 0 must end as
+    status G holding the inclusive prefixes the paper prints.
+    """
+    g = read_golden("lookback_fig7.txt")
+    tile = 16
+    keys = []
+    for c in g["local_counts"]:
+        keys += [0] * c + [1] * (tile - c)
+    keys = np.array(keys, dtype=np.uint32)
+    st = oracle.pass_status(keys, 0, 4, tile)
+    for t, want in enumerate(g["inclusive"]):
+        s, v = oracle.status_unpack(int(st[t, 0]))
+        assert s == oracle.STATUS_G and v == want
+    # digit 1 is the complement within each tile
+    ones = np.cumsum([tile - c for c in g["local_counts"]])
+    for t in range(5):
+        assert oracle.status_unpack(int(st[t, 1])) == (oracle.STATUS_G, int(ones[t]))
+
+
+def test_status_word_layout():
+    """Figure 6: two high bits status, 30 low bits value."""
+    assert oracle.status_pack(oracle.STATUS_G, 35) == (2 << 30) | 35
+    assert oracle.status_pack(oracle.STATUS_L, (1 << 30) - 1) == 0x7FFFFFFF
+    assert oracle.status_unpack(0x80000023) == (2, 35)
+    assert oracle.status_unpack(0x40000000) == (1, 0)
+    assert oracle.status_unpack(0) == (0, 0)
+
+
+def test_num_places_closed_form():
+    """Section 1: p = ceil(k/d)."""
+    for k in (32, 64):
+        for d in range(1, 17):
+            assert oracle.num_places(0, k, d) == -(-k // d)
+    assert oracle.num_places(0, 32, 8) == 4
+    assert oracle.num_places(0, 32, 7) == 5  # Table 2 prints 4 here; see the reading of p
+    assert oracle.num_places(0, 64, 8) == 8
+    assert oracle.num_places(5, 5, 8) == 0
+
+
+def test_memory_operation_model():
+    """Section 3: (2p+1)n vs 3pn operations; 1.33x at p = 4, 1.5x ceiling."""
+    g = read_golden("memory_ops_model.txt")
+    p = g["p"][0]
+    assert round(3 * p / (2 * p + 1), 2) == g["reduction"][0]
+    assert abs(3 * 10**6 / (2 * 10**6 + 1) - g["ceiling"][0]) < 1e-5
+
+
+# --------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("key_bits", [32, 64])
+def test_sort_matches_brute_force_random(key_bits):
+    rng = random.Random(1234 + key_bits)
+    dt = np.uint32 if key_bits == 32 else np.uint64
+    for _ in range(300):
+        n = rng.randint(0, 70)
+        begin = rng.randint(0, key_bits)
+        end = rng.randint(begin, key_bits)
+        d = rng.randint(1, 11)
+        span = rng.choice([2, 7, 1 << 12, (1 << key_bits) - 1])
+        keys = np.array([rng.randint(0, span) for _ in range(n)], dtype=dt)
+        keys <<= dt(rng.randint(0, 3))
+        vals = np.arange(n, dtype=np.uint32)
+        ko, vo = oracle.sort(keys, vals, begin, end, d)
+        bk, bv = brute_sort(keys, vals, begin, end)
+        assert np.array_equal(ko, bk), (n, begin, end, d)
+        assert np.array_equal(vo, bv), (n, begin, end, d)
+
+
+def test_exhaustive_small_sequences():
+    """Every sequence of length <= 5 over 3-bit keys, for d = 1, 2, 3 and
+    several bit ranges, against brute force. All sequences go through the
+    segmented oracle at once (one segment each), which also pins it."""
+    seqs = []
+    for length in range(0, 6):
+        seqs.extend(itertools.product(range(8), repeat=length))
+    lengths = np.array([len(s) for s in seqs], dtype=np.int64)
+    off = np.zeros(len(seqs) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(lengths)
+    keys = np.array([x for s in seqs for x in s], dtype=np.uint32)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    for (begin, end) in [(0, 3), (1, 3), (0, 2), (2, 3), (0, 32)]:
+        for d in (1, 2, 3):
+            ko, vo = oracle.sort_segments(keys, off, vals, begin, end, d)
+            for s in range(len(seqs)):
+                a, b = int(off[s]), int(off[s + 1])
+                if b - a < 2:
+                    assert np.array_equal(ko[a:b], keys[a:b])
+                    continue
+                bk, bv = brute_sort(keys[a:b], vals[a:b], begin, end)
+                assert np.array_equal(ko[a:b], bk)
+                assert np.array_equal(vo[a:b], bv)
+
+
+@pytest.mark.parametrize("key_bits,d", [(32, 8), (32, 5), (64, 8), (64, 7)])
+def test_each_pass_is_stable_sort_by_its_digit(key_bits, d):
+    """Pass j output = stable sort, by digit j alone, of pass j-1 output."""
+    dt = np.uint32 if key_bits == 32 else np.uint64
+    rng = np.random.default_rng(7)
+    keys = rng.integers(0, 1 << 62, 3000, dtype=np.uint64).astype(dt)
+    begin, end = 3, key_bits - 2
+    ko, _, passes = oracle.sort(keys, None, begin, end, d, return_passes=True)
+    p = oracle.num_places(begin, end, d)
+    assert passes.shape == (p, keys.size)
+    prev = keys
+    for j in range(p):
+        lo = begin + j * d
+        hi = min(lo + d, end)
+        order = sorted(range(prev.size), key=lambda i: field(prev[i], lo, hi))
+        assert np.array_equal(passes[j], prev[order]), j
+        prev = passes[j]
+    assert np.array_equal(ko, prev)
+
+
+# --------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("key_bits", [32, 64])
+def test_histogram_invariants(key_bits):
+    dt = np.uint32 if key_bits == 32 else np.uint64
+    rng = np.random.default_rng(11)
+    keys = rng.integers(0, 1 << 63, 20000, dtype=np.uint64).astype(dt)
+    for d in (4, 8, 11):
+        hist = oracle.histograms(keys, 0, key_bits, d)
+        off = oracle.exclusive_sums(hist)
+        p = oracle.num_places(0, key_bits, d)
+        assert hist.shape == (p, 1 << d)
+        assert np.all(hist.sum(axis=1) == keys.size)  # totals equal n at every place
+        assert np.all(off[:, -1] + hist[:, -1] == keys.size)
+        # order independence (Section 3: counts depend only on the multiset)
+        perm = rng.permutation(keys.size)
+        assert np.array_equal(oracle.histograms(keys[perm], 0, key_bits, d), hist)
+        # independent count with numpy for every place
+        for j in range(p):
+            lo = j * d
+            w = min(d, key_bits - lo)
+            dig = ((keys.astype(np.uint64) >> np.uint64(lo)) & np.uint64((1 << w) - 1))
+            assert np.array_equal(np.bincount(dig.astype(np.int64), minlength=1 << d), hist[j])
+
+
+@pytest.mark.parametrize("key_bits", [32, 64])
+def test_full_width_keys_only_equals_numpy_sort(key_bits):
+    """Special case: full width and no values reduces to an ordinary sort."""
+    dt = np.uint32 if key_bits == 32 else np.uint64
+    rng = np.random.default_rng(5)
+    for n in (0, 1, 2, 1000, 65537):
+        keys = rng.integers(0, 1 << 64, n, dtype=np.uint64).astype(dt)
+        ko, _ = oracle.sort(keys, None, 0, key_bits, 8)
+        assert np.array_equal(ko, np.sort(keys))
+
+
+def test_pairs_permutation_sorted_stable():
+    rng = np.random.default_rng(3)
+    n = 50000
+    keys = (rng.integers(0, 1 << 32, n, dtype=np.uint64) & np.uint64(0xF0F0)).astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = oracle.sort(keys, vals, 0, 32, 8)
+    assert np.array_equal(np.sort(vo), vals)  # a permutation
+    assert np.array_equal(ko, keys[vo])  # keys travel with their values
+    assert np.all(ko[1:] >= ko[:-1])  # sorted
+    same = ko[1:] == ko[:-1]
+    assert np.all(vo[1:][same] > vo[:-1][same])  # stable
+
+
+def test_partial_bit_range_carries_whole_keys():
+    rng = np.random.default_rng(9)
+    keys = rng.integers(0, 1 << 32, 5000, dtype=np.uint64).astype(np.uint32)
+    ko, _ = oracle.sort(keys, None, 8, 20, 8)
+    assert np.array_equal(np.sort(ko), np.sort(keys))
+    f = (ko >> np.uint32(8)) & np.uint32(0xFFF)
+    assert np.all(f[1:] >= f[:-1])
+    # a stable sort by the field equals numpy's stable argsort of the field
+    fi = (keys >> np.uint32(8)) & np.uint32(0xFFF)
+    assert np.array_equal(ko, keys[np.argsort(fi, kind="stable")])
+
+
+def test_begin_equals_end_copies():
+    keys = np.array([5, 3, 9], dtype=np.uint32)
+    ko, vo = oracle.sort(keys, np.array([0, 1, 2], dtype=np.uint32), 7, 7, 8)
+    assert ko.tolist() == [5, 3, 9] and vo.tolist() == [0, 1, 2]
+
+
+def test_segments_independent():
+    rng = np.random.default_rng(21)
+    lengths = rng.integers(0, 300, 60)
+    off = np.zeros(61, dtype=np.uint64)
+    off[1:] = np.cumsum(lengths)
+    n = int(off[-1])
+    keys = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = oracle.sort_segments(keys, off, vals, 0, 32, 8)
+    for s in range(60):
+        a, b = int(off[s]), int(off[s + 1])
+        assert np.all((vo[a:b] >= a) & (vo[a:b] < b))  # no element crosses a boundary
+        assert np.array_equal(ko[a:b], keys[a:b][np.argsort(keys[a:b], kind="stable")])
+    with pytest.raises(ValueError):
+        bad = off.copy()
+        bad[-1] += 1
+        oracle.sort_segments(keys, bad, vals)
+
+
+def test_pass_status_invariants():
+    """Final chained-scan state: all G; consecutive differences are the
+    tile's own digit counts (np.bincount); the last tile holds the totals."""
+    rng = np.random.default_rng(13)
+    tile = 96
+    keys = rng.integers(0, 1 << 32, 96 * 7 + 13, dtype=np.uint64).astype(np.uint32)
+    lo, width = 4, 6
+    st = oracle.pass_status(keys, lo, width, tile)
+    g = -(-keys.size // tile)
+    assert st.shape == (g, 1 << width)
+    assert np.all(st >> np.uint32(30) == oracle.STATUS_G)
+    vals = (st & np.uint32(0x3FFFFFFF)).astype(np.int64)
+    dig = ((keys >> np.uint32(lo)) & np.uint32((1 << width) - 1)).astype(np.int64)
+    prev = np.zeros(1 << width, dtype=np.int64)
+    for t in range(g):
+        cnt = np.bincount(dig[t * tile:(t + 1) * tile], minlength=1 << width)
+        assert np.array_equal(vals[t] - prev, cnt)
+        prev = vals[t]
+    assert np.array_equal(vals[-1], np.bincount(dig, minlength=1 << width))

@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module only produces input data. It holds none of the sorting method's
+arithmetic, so both the CPU oracle and the GPU path may consume what it makes
+without sharing any code with each other.
+
+Random source: SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), used as a counter-based
+generator::
+
+    mix64(z)      = the SplitMix64 finaliser
+    base(s, k)    = mix64((s << 8) | k)
+    word(s, k, i) = mix64(base(s, k) + (i + 1) * 0x9E3779B97F4A7C15)
+
+A 32-bit key is the high half of a word, a 64-bit key is the whole word.
+
+Key distributions follow the Thearling-Smith entropy bands the paper uses
+(Section 4: each key is the bitwise AND of q independent uniform words, so the
+entropy per bit is H(2^-q), Table 1), plus the extra shapes the learned-config
+sweep needs (Zipf, presorted, reverse-sorted, 16 distinct values) and the
+log-normal segment lengths of the batched segmented workload.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+# Elements generated per numpy chunk; bounds temporary memory to ~100 MiB.
+_CHUNK = 1 << 22
+
+
+def mix64(z):
+    """SplitMix64 finaliser on a numpy uint64 array (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def mix64_int(z: int) -> int:
+    """Pure-Python SplitMix64 finaliser (reference for the vectorised form)."""
+    mask = (1 << 64) - 1
+    z &= mask
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+    return z ^ (z >> 31)
+
+
+def base(seed: int, stream: int) -> np.uint64:
+    return np.uint64(mix64_int(((seed << 8) | stream) & ((1 << 64) - 1)))
+
+
+def words(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """word(seed, stream, i) for i in [start, start + n) as uint64."""
+    out = np.empty(n, dtype=np.uint64)
+    b = base(seed, stream)
+    for c0 in range(0, n, _CHUNK):
+        c1 = min(n, c0 + _CHUNK)
+        i = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            out[c0:c1] = mix64(b + i * GAMMA)
+    return out
+
+
+def _narrow(w: np.ndarray, key_bits: int) -> np.ndarray:
+    if key_bits == 64:
+        return w
+    if key_bits == 32:
+        return (w >> np.uint64(32)).astype(np.uint32)
+    raise ValueError("key_bits must be 32 or 64")
+
+
+def uniform(seed: int, n: int, key_bits: int = 32, stream: int = 1) -> np.ndarray:
+    """Uniform keys: the entropy band q = 1."""
+    return _narrow(words(seed, stream, n), key_bits)
+
+
+def and_of_q(seed: int, q: int, n: int, key_bits: int = 32) -> np.ndarray:
+    """Bitwise AND of q independent uniform words (streams 1..q).
+
+    Each bit is set with probability 2^-q, so the entropy per bit is
+    H(2^-q) with H the binary entropy (Section 4 and Table 1).
+    """
+    if q < 1:
+        raise ValueError("q >= 1")
+    dt = np.uint32 if key_bits == 32 else np.uint64
+    out = np.empty(n, dtype=dt)
+    for c0 in range(0, n, _CHUNK):
+        c1 = min(n, c0 + _CHUNK)
+        acc = words(seed, 1, c1 - c0, start=c0)
+        for k in range(2, q + 1):
+            acc &= words(seed, k, c1 - c0, start=c0)
+        out[c0:c1] = _narrow(acc, key_bits)
+    return out
+
+
+def all_equal(seed: int, n: int, key_bits: int = 32) -> np.ndarray:
+    """Every key equal to word(seed, 9, 0)."""
+    v = _narrow(words(seed, 9, 1), key_bits)[0]
+    return np.full(n, v, dtype=v.dtype)
+
+
+def unit_doubles(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """Doubles in (0, 1): the top 53 bits of each word, offset by half an ulp."""
+    w = words(seed, stream, n, start)
+    return ((w >> np.uint64(11)).astype(np.float64) + 0.5) * (1.0 / (1 << 53))
+
+
+def zipf_keys(seed: int, n: int, key_bits: int = 32, s: float = 1.1,
+              support: int = 1 << 20) -> np.ndarray:
+    """Zipf(s) over ranks 1..support; key = rank - 1 (inverse CDF, binary search)."""
+    ranks = np.arange(1, support + 1, dtype=np.float64)
+    cdf = np.cumsum(ranks ** (-s))
+    cdf /= cdf[-1]
+    u = unit_doubles(seed, 1, n)
+    k = np.searchsorted(cdf, u, side="left")
+    k = np.minimum(k, support - 1)
+    return k.astype(np.uint32 if key_bits == 32 else np.uint64)
+
+
+def presorted(seed: int, n: int, key_bits: int = 32) -> np.ndarray:
+    return np.sort(uniform(seed, n, key_bits))
+
+
+def reverse_sorted(seed: int, n: int, key_bits: int = 32) -> np.ndarray:
+    return np.sort(uniform(seed, n, key_bits))[::-1].copy()
+
+
+def distinct16(seed: int, n: int, key_bits: int = 32) -> np.ndarray:
+    """16 distinct values word(seed, 100, 0..15); index = top 4 bits of word(seed, 1, i)."""
+    table = _narrow(words(seed, 100, 16), key_bits)
+    idx = (words(seed, 1, n) >> np.uint64(60)).astype(np.int64)
+    return table[idx]
+
+
+DISTRIBUTIONS = ("and1", "and2", "and3", "and4", "zipf", "presorted", "reverse", "distinct16")
+
+
+def make_keys(dist: str, seed: int, n: int, key_bits: int = 32) -> np.ndarray:
+    """Keys of one named distribution of the learned-config sweep."""
+    if dist.startswith("and"):
+        return and_of_q(seed, int(dist[3:]), n, key_bits)
+    if dist == "uniform":
+        return uniform(seed, n, key_bits)
+    if dist == "zipf":
+        return zipf_keys(seed, n, key_bits)
+    if dist == "presorted":
+        return presorted(seed, n, key_bits)
+    if dist == "reverse":
+        return reverse_sorted(seed, n, key_bits)
+    if dist == "distinct16":
+        return distinct16(seed, n, key_bits)
+    if dist == "equal":
+        return all_equal(seed, n, key_bits)
+    raise ValueError(f"unknown distribution {dist!r}")
+
+
+def sweep_case(seed: int):
+    """(n, key_bits, dist) of one learned-config sweep input.
+
+    n = round(2^(17 + 11 u)) with u from word(seed, 300, 0); key widths alternate
+    between 32 and 64 bits and distributions cycle over DISTRIBUTIONS by seed.
+    """
+    u = float(unit_doubles(seed, 300, 1)[0])
+    n = int(round(2.0 ** (17.0 + 11.0 * u)))
+    key_bits = 32 if seed % 2 == 0 else 64
+    dist = DISTRIBUTIONS[(seed // 2) % len(DISTRIBUTIONS)]
+    return n, key_bits, dist
+
+
+def lognormal_segment_lengths(num_segments: int = 20000, median: float = 2000.0,
+                              sigma: float = 1.5, cap: int = 1 << 22, seed: int = 4,
+                              total: int | None = 1 << 26) -> np.ndarray:
+    """Segment lengths L_s = min(cap, round(exp(ln(median) + sigma * z_s))).
+
+    z_s is a standard normal from Box-Muller on consecutive unit doubles of
+    stream 200. When `total` is given, every length is scaled by one common
+    factor and rounded so that the lengths add up to `total` exactly (largest
+    remainders receive the leftover units, ties broken by lower index).
+    """
+    u = unit_doubles(seed, 200, 2 * num_segments)
+    u1, u2 = u[0::2], u[1::2]
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+    raw = np.minimum(float(cap), np.rint(np.exp(math.log(median) + sigma * z)))
+    if total is None:
+        return raw.astype(np.int64)
+    scaled = raw * (float(total) / raw.sum())
+    base_len = np.floor(scaled).astype(np.int64)
+    short = int(total - base_len.sum())
+    if short > 0:
+        frac = scaled - base_len
+        order = np.lexsort((np.arange(num_segments), -frac))
+        base_len[order[:short]] += 1
+    return base_len
+
+
+def offsets_from_lengths(lengths: np.ndarray) -> np.ndarray:
+    off = np.zeros(len(lengths) + 1, dtype=np.int64)
+    np.cumsum(lengths, out=off[1:])
+    return off
+
+
+def binary_entropy(p: float) -> float:
+    if p <= 0.0 or p >= 1.0:
+        return 0.0
+    return -(p * math.log2(p) + (1 - p) * math.log2(1 - p))
+
+
+def per_bit_entropy(keys: np.ndarray) -> float:
+    """Mean over bit positions of the empirical binary entropy of that bit."""
+    bits = keys.dtype.itemsize * 8
+    ks = keys.astype(np.uint64)
+    h = 0.0
+    for b in range(bits):
+        p1 = float(np.count_nonzero((ks >> np.uint64(b)) & np.uint64(1))) / len(ks)
+        h += binary_entropy(p1)
+    return h / bits
