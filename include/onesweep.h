@@ -1,0 +1,170 @@
+/*
+ * onesweep.h: C ABI of an MI355X (gfx950) implementation of Onesweep, the
+ * single-pass LSD radix sort of Adinets and Merrill (arXiv 2206.01784).
+ *
+ * The sort (Section 3) runs as three phases:
+ *   1. one upfront pass that histograms every digit place at once,
+ *   2. an exclusive sum of each place's histogram (global bin offsets),
+ *   3. one chained-scan digit-binning kernel per digit place, which ranks the
+ *      keys of a tile, obtains the tile's bin-relative offsets by decoupled
+ *      look-back over per-tile status words and scatters keys (and values)
+ *      stably, for about 2n global memory operations per place.
+ *
+ * Conventions shared by every entry point:
+ *  - Device pointers (d_*) are caller-owned device memory; the library never
+ *    allocates, frees or synchronises on the sort path and keeps no pointer
+ *    once the enqueued work has completed.
+ *  - Two-phase temporary storage: when d_temp is NULL the call only writes the
+ *    required size to *temp_bytes and enqueues nothing (no GPU is touched).
+ *    d_temp must be 256-byte aligned and at least that large.
+ *  - All work is enqueued on `stream` (0 = the null stream) and is
+ *    asynchronous; results are valid after the caller synchronises. The
+ *    enqueued sequence uses kernels only (no memset or memcpy nodes), so a
+ *    caller may capture it into a HIP graph.
+ *  - Keys are unsigned 32- or 64-bit integers ordered ascending by the bit
+ *    field [begin_bit, end_bit) (0 <= begin_bit <= end_bit <= key_bits); the
+ *    whole key word is carried to the output. Values are opaque 32-bit
+ *    payloads that travel with their keys.
+ *  - Digit places are 8 bits wide (r = 256 bins); place j covers bits
+ *    [begin_bit + 8j, min(begin_bit + 8j + 8, end_bit)), so
+ *    p = ceil((end_bit - begin_bit) / 8) places (Section 1).
+ *  - The output is always stable, because an LSD sort is stable by
+ *    construction (Section 1); the `stable` argument is accepted for
+ *    interface symmetry and ignored.
+ *  - n must be below 2^30: the chained-scan status words hold 30-bit values
+ *    (Section 3, "Handling very large problems"). Larger n returns
+ *    ONESWEEP_ERROR_TOO_LARGE.
+ *  - Errors are returned as status codes; nothing is enqueued when argument
+ *    validation fails. onesweep_last_error() describes the last failure of
+ *    the calling thread.
+ */
+#ifndef ONESWEEP_H
+#define ONESWEEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *onesweep_stream_t; /* same type as hipStream_t */
+
+typedef enum {
+    ONESWEEP_SUCCESS = 0,
+    ONESWEEP_ERROR_INVALID_VALUE = 1,     /* bad pointer, width, bit range, overlap */
+    ONESWEEP_ERROR_TOO_LARGE = 2,         /* n >= 2^30 */
+    ONESWEEP_ERROR_INSUFFICIENT_TEMP = 3, /* *temp_bytes below the required size */
+    ONESWEEP_ERROR_HIP = 4,               /* a HIP runtime call failed */
+    ONESWEEP_ERROR_UNSUPPORTED = 5        /* configuration not built into the library */
+} onesweep_status_t;
+
+/* Kinds of kernel launch reported through onesweep_trace_t. */
+typedef enum {
+    ONESWEEP_KERNEL_RESET = 0,     /* clears histograms, tile counters, status words */
+    ONESWEEP_KERNEL_HISTOGRAM = 1, /* phase 1: all-place histogram */
+    ONESWEEP_KERNEL_SCAN = 2,      /* phase 2: exclusive sums and pass plan */
+    ONESWEEP_KERNEL_BINNING = 3,   /* phase 3: one chained-scan binning pass */
+    ONESWEEP_KERNEL_COPY = 4       /* final copy when no pass (or an odd count) ran */
+} onesweep_kernel_kind_t;
+
+#define ONESWEEP_TRACE_MAX 64
+
+/*
+ * Optional per-launch timing. The caller creates 2 * capacity HIP events with
+ * timing enabled and passes their handles in `events`; the library records
+ * events[2i] on the stream just before launch i and events[2i + 1] just after
+ * it, sets kinds[i] and sets `count` to the number of launches recorded
+ * (launches beyond capacity are not recorded). Elapsed times are read by the
+ * caller with hipEventElapsedTime after synchronising.
+ */
+typedef struct {
+    void **events;   /* hipEvent_t handles, 2 * capacity of them */
+    int capacity;    /* launches that can be recorded */
+    int count;       /* out: launches recorded by the last call */
+    int kinds[ONESWEEP_TRACE_MAX]; /* out: onesweep_kernel_kind_t per launch */
+} onesweep_trace_t;
+
+/*
+ * Kernel configuration. A NULL config, or 0 in a field, selects the default
+ * for the key width and the presence of values. block_threads x
+ * items_per_thread is the binning tile size T (Section 3 dispatches one
+ * workgroup per tile). Only combinations compiled into the library are
+ * accepted; others return ONESWEEP_ERROR_UNSUPPORTED.
+ */
+typedef struct {
+    int digit_bits;          /* 0 or 8 */
+    int block_threads;       /* binning workgroup size: 256, 512 or 1024 */
+    int items_per_thread;    /* binning items per thread */
+    int hist_blocks_per_cu;  /* histogram grid = CUs x this (persistent, tile-cyclic) */
+    onesweep_trace_t *trace; /* optional launch timing, may be NULL */
+} onesweep_config_t;
+
+/*
+ * Sort n keys (Section 3, all three phases).
+ * d_keys_in may equal d_keys_out (in-place); partial overlap is invalid.
+ * key_bits is 32 or 64. Null pointers are accepted when n == 0.
+ */
+onesweep_status_t onesweep_sort_keys(void *d_temp, size_t *temp_bytes, const void *d_keys_in,
+                                     void *d_keys_out, size_t n, int key_bits, int begin_bit,
+                                     int end_bit, int stable, const onesweep_config_t *cfg,
+                                     onesweep_stream_t stream);
+
+/*
+ * Sort n (key, value) pairs: keys as in onesweep_sort_keys, values are
+ * uint32 and follow their keys (Section 3: values are loaded after the keys
+ * are ranked and scattered with the same destinations).
+ */
+onesweep_status_t onesweep_sort_pairs(void *d_temp, size_t *temp_bytes, const void *d_keys_in,
+                                      void *d_keys_out, const uint32_t *d_vals_in,
+                                      uint32_t *d_vals_out, size_t n, int key_bits,
+                                      int begin_bit, int end_bit, int stable,
+                                      const onesweep_config_t *cfg, onesweep_stream_t stream);
+
+/*
+ * Phase 1 alone (Section 3, upfront histogram kernel): d_hist[j * 256 + v]
+ * receives the number of keys whose digit at place j is v, for all
+ * p = ceil((end_bit - begin_bit) / 8) places. d_hist must hold p * 256
+ * uint32 words; it is cleared first. n < 2^30.
+ */
+onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits, int begin_bit,
+                                     int end_bit, uint32_t *d_hist,
+                                     const onesweep_config_t *cfg, onesweep_stream_t stream);
+
+/*
+ * Phase 3, one binning iteration (Section 3, chained scan digit-binning
+ * kernel): stably scatter the n keys (and values, when d_src_vals is not
+ * NULL) of src into dst by the digit (key >> shift) & (2^width - 1), with
+ * d_bin_offsets[v] (256 uint32, device) the global start of bin v, which is
+ * the exclusive sum of the digit counts. 1 <= width <= 8,
+ * shift + width <= key_bits. src and dst must not overlap.
+ * Temp layout (documented so tests can read the chained-scan state): bytes
+ * [0, 256) hold the tile counter, then ceil(n / T) rows of 256 uint32 status
+ * words (row = tile, column = digit; Figure 6 layout: 2-bit status above a
+ * 30-bit value). After the pass every word holds status G (2) and the tile's
+ * inclusive prefix count.
+ */
+onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
+                                        const void *d_src_keys, void *d_dst_keys,
+                                        const uint32_t *d_src_vals, uint32_t *d_dst_vals,
+                                        size_t n, int key_bits, int shift, int width,
+                                        const uint32_t *d_bin_offsets,
+                                        const onesweep_config_t *cfg,
+                                        onesweep_stream_t stream);
+
+/* Binning tile size T = block_threads x items_per_thread that `cfg` resolves
+ * to for this key width and value presence; 0 if the config is unsupported.
+ * Pure host computation. */
+size_t onesweep_tile_items(int key_bits, int has_values, const onesweep_config_t *cfg);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char *onesweep_last_error(void);
+
+/* Library version string. */
+const char *onesweep_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ONESWEEP_H */

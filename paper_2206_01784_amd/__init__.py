@@ -1,0 +1,241 @@
+"""Python binding of the Onesweep HIP library for MI355X (gfx950).
+
+Argument marshalling only: every step of the sort runs in the HIP kernels of
+libonesweep.so, reached through its C ABI (include/onesweep.h). PyTorch
+supplies device memory and the current stream. There is no CPU fallback: if
+the library is not built, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libonesweep.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -m paper_2206_01784_amd.build, or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SUCCESS = 0
+ERROR_INVALID_VALUE = 1
+ERROR_TOO_LARGE = 2
+ERROR_INSUFFICIENT_TEMP = 3
+ERROR_HIP = 4
+ERROR_UNSUPPORTED = 5
+
+KERNEL_RESET, KERNEL_HISTOGRAM, KERNEL_SCAN, KERNEL_BINNING, KERNEL_COPY = range(5)
+KERNEL_NAMES = ("reset", "histogram", "scan", "binning", "copy")
+TRACE_MAX = 64
+RADIX_BITS = 8
+RADIX = 256
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("events", ctypes.POINTER(ctypes.c_void_p)), ("capacity", ctypes.c_int),
+                ("count", ctypes.c_int), ("kinds", ctypes.c_int * TRACE_MAX)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("digit_bits", ctypes.c_int), ("block_threads", ctypes.c_int),
+                ("items_per_thread", ctypes.c_int), ("hist_blocks_per_cu", ctypes.c_int),
+                ("trace", ctypes.POINTER(Trace))]
+
+
+_vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+_szp = ctypes.POINTER(ctypes.c_size_t)
+_cfgp = ctypes.POINTER(Config)
+
+_lib.onesweep_sort_keys.argtypes = [_vp, _szp, _vp, _vp, _sz, _i32, _i32, _i32, _i32, _cfgp, _vp]
+_lib.onesweep_sort_pairs.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _i32, _i32, _i32, _i32,
+                                     _cfgp, _vp]
+_lib.onesweep_histogram.argtypes = [_vp, _sz, _i32, _i32, _i32, _vp, _cfgp, _vp]
+_lib.onesweep_binning_pass.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _i32, _i32, _i32, _vp,
+                                       _cfgp, _vp]
+_lib.onesweep_tile_items.argtypes = [_i32, _i32, _cfgp]
+_lib.onesweep_tile_items.restype = _sz
+_lib.onesweep_last_error.restype = ctypes.c_char_p
+_lib.onesweep_version.restype = ctypes.c_char_p
+for _f in ("onesweep_sort_keys", "onesweep_sort_pairs", "onesweep_histogram",
+           "onesweep_binning_pass"):
+    getattr(_lib, _f).restype = _i32
+
+
+class OnesweepError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"onesweep error {code}: {message}")
+        self.code = code
+
+
+def library():
+    """The loaded ctypes handle of libonesweep.so."""
+    return _lib
+
+
+def version() -> str:
+    return _lib.onesweep_version().decode()
+
+
+def _check(code: int):
+    if code != SUCCESS:
+        raise OnesweepError(code, _lib.onesweep_last_error().decode())
+
+
+def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,
+                digit_bits: int = 0, trace: Trace | None = None) -> Config:
+    c = Config(digit_bits, block_threads, items_per_thread, hist_blocks_per_cu, None)
+    if trace is not None:
+        c.trace = ctypes.pointer(trace)
+    return c
+
+
+def _cfg_ptr(cfg):
+    return None if cfg is None else ctypes.byref(cfg)
+
+
+def _key_bits(t: torch.Tensor) -> int:
+    if t.dtype == torch.uint32:
+        return 32
+    if t.dtype == torch.uint64:
+        return 64
+    raise TypeError(f"keys must be torch.uint32 or torch.uint64, got {t.dtype}")
+
+
+def _dev_ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() else None
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def tile_items(key_bits: int = 32, has_values: bool = False, config: Config | None = None) -> int:
+    return int(_lib.onesweep_tile_items(key_bits, int(has_values), _cfg_ptr(config)))
+
+
+def sort_temp_bytes(n: int, key_bits: int = 32, has_values: bool = False, begin_bit: int = 0,
+                    end_bit: int | None = None, config: Config | None = None) -> int:
+    """Temporary storage a sort of n keys needs (pure host computation)."""
+    end_bit = key_bits if end_bit is None else end_bit
+    size = ctypes.c_size_t(0)
+    if has_values:
+        _check(_lib.onesweep_sort_pairs(None, ctypes.byref(size), None, None, None, None, n,
+                                        key_bits, begin_bit, end_bit, 1, _cfg_ptr(config), None))
+    else:
+        _check(_lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, n, key_bits,
+                                       begin_bit, end_bit, 1, _cfg_ptr(config), None))
+    return int(size.value)
+
+
+def _temp(temp, need, device):
+    if temp is None:
+        return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    if temp.numel() < need:
+        raise ValueError(f"temp holds {temp.numel()} bytes, needs {need}")
+    return temp
+
+
+def sort_keys(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
+              out: torch.Tensor | None = None, temp: torch.Tensor | None = None,
+              config: Config | None = None, stream=None) -> torch.Tensor:
+    """Stable ascending sort of uint32/uint64 keys by bits [begin_bit, end_bit)."""
+    kb = _key_bits(keys)
+    end_bit = kb if end_bit is None else end_bit
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    need = sort_temp_bytes(n, kb, False, begin_bit, end_bit, config)
+    temp = _temp(temp, need, keys.device)
+    size = ctypes.c_size_t(temp.numel())
+    _check(_lib.onesweep_sort_keys(_dev_ptr(temp), ctypes.byref(size), _dev_ptr(keys),
+                                   _dev_ptr(out), n, kb, begin_bit, end_bit, 1,
+                                   _cfg_ptr(config), _stream(stream)))
+    return out
+
+
+def sort_pairs(keys: torch.Tensor, values: torch.Tensor, begin_bit: int = 0,
+               end_bit: int | None = None, keys_out: torch.Tensor | None = None,
+               values_out: torch.Tensor | None = None, temp: torch.Tensor | None = None,
+               config: Config | None = None, stream=None):
+    """Stable sort of (key, uint32 value) pairs; returns (keys_out, values_out)."""
+    kb = _key_bits(keys)
+    if values.dtype != torch.uint32:
+        raise TypeError("values must be torch.uint32")
+    if values.numel() != keys.numel():
+        raise ValueError("keys and values differ in length")
+    end_bit = kb if end_bit is None else end_bit
+    n = keys.numel()
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    values_out = torch.empty_like(values) if values_out is None else values_out
+    need = sort_temp_bytes(n, kb, True, begin_bit, end_bit, config)
+    temp = _temp(temp, need, keys.device)
+    size = ctypes.c_size_t(temp.numel())
+    _check(_lib.onesweep_sort_pairs(_dev_ptr(temp), ctypes.byref(size), _dev_ptr(keys),
+                                    _dev_ptr(keys_out), _dev_ptr(values), _dev_ptr(values_out), n,
+                                    kb, begin_bit, end_bit, 1, _cfg_ptr(config), _stream(stream)))
+    return keys_out, values_out
+
+
+def histogram(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
+              out: torch.Tensor | None = None, config: Config | None = None,
+              stream=None) -> torch.Tensor:
+    """Phase 1 alone: uint32 digit counts of every 8-bit place, shape (p, 256)."""
+    kb = _key_bits(keys)
+    end_bit = kb if end_bit is None else end_bit
+    p = (end_bit - begin_bit + RADIX_BITS - 1) // RADIX_BITS
+    if out is None:
+        out = torch.empty((max(p, 0), RADIX), dtype=torch.uint32, device=keys.device)
+    if p == 0:
+        return out
+    _check(_lib.onesweep_histogram(_dev_ptr(keys), keys.numel(), kb, begin_bit, end_bit,
+                                   _dev_ptr(out), _cfg_ptr(config), _stream(stream)))
+    return out
+
+
+def binning_pass_temp_bytes(n: int, key_bits: int = 32, has_values: bool = False,
+                            config: Config | None = None) -> int:
+    size = ctypes.c_size_t(0)
+    dummy = ctypes.c_void_p(1) if has_values else None
+    _check(_lib.onesweep_binning_pass(None, ctypes.byref(size), None, None, dummy, dummy, n,
+                                      key_bits, 0, RADIX_BITS, None, _cfg_ptr(config), None))
+    return int(size.value)
+
+
+def binning_pass(src: torch.Tensor, bin_offsets: torch.Tensor, shift: int, width: int = 8,
+                 dst: torch.Tensor | None = None, src_values: torch.Tensor | None = None,
+                 dst_values: torch.Tensor | None = None, temp: torch.Tensor | None = None,
+                 config: Config | None = None, stream=None):
+    """Phase 3, one iteration: stable scatter of src by digit (key >> shift) & (2^width - 1).
+
+    Returns (dst, dst_values, temp); temp holds the tile counter and the
+    chained-scan status words (see onesweep_binning_pass in include/onesweep.h).
+    """
+    kb = _key_bits(src)
+    if bin_offsets.dtype != torch.uint32 or bin_offsets.numel() != RADIX:
+        raise ValueError("bin_offsets must be 256 uint32")
+    n = src.numel()
+    has_values = src_values is not None
+    dst = torch.empty_like(src) if dst is None else dst
+    if has_values and dst_values is None:
+        dst_values = torch.empty_like(src_values)
+    need = binning_pass_temp_bytes(n, kb, has_values, config)
+    temp = _temp(temp, need, src.device)
+    size = ctypes.c_size_t(temp.numel())
+    _check(_lib.onesweep_binning_pass(_dev_ptr(temp), ctypes.byref(size), _dev_ptr(src),
+                                      _dev_ptr(dst), _dev_ptr(src_values), _dev_ptr(dst_values),
+                                      n, kb, shift, width, _dev_ptr(bin_offsets),
+                                      _cfg_ptr(config), _stream(stream)))
+    return dst, dst_values, temp

@@ -1,0 +1,463 @@
+// C ABI of the Onesweep library: argument validation, temporary-storage
+// layout, the launch sequence of the three phases (Section 3) and optional
+// per-launch event tracing. No allocation, no synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+
+#include "../../include/onesweep.h"
+#include "internal.hpp"
+
+namespace onesweep {
+namespace {
+
+thread_local char g_error[512] = "";
+
+onesweep_status_t fail(onesweep_status_t code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_error, sizeof(g_error), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+onesweep_status_t hip_fail(hipError_t e, const char *what) {
+  return fail(ONESWEEP_ERROR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxN = size_t(1) << 30;  // 30-bit status values
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int num_places(int begin_bit, int end_bit) {
+  return (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+}
+
+// Compute units of the current device, cached per device id.
+std::atomic<int> g_cus[64];
+
+onesweep_status_t device_cus(int *cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev >= 0 && dev < 64) {
+    int c = g_cus[dev].load(std::memory_order_relaxed);
+    if (c > 0) {
+      *cus = c;
+      return ONESWEEP_SUCCESS;
+    }
+  }
+  int c = 0;
+  e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  if (c <= 0) c = 1;
+  if (dev >= 0 && dev < 64) g_cus[dev].store(c, std::memory_order_relaxed);
+  *cus = c;
+  return ONESWEEP_SUCCESS;
+}
+
+// Resolved kernel configuration.
+struct Resolved {
+  BinningShape shape;
+  int hist_blocks_per_cu;
+  onesweep_trace_t *trace;
+};
+
+onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t *cfg,
+                          Resolved *r) {
+  r->shape = binning_default_shape(key_bits, has_values);
+  r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
+  r->trace = nullptr;
+  if (cfg != nullptr) {
+    if (cfg->digit_bits != 0 && cfg->digit_bits != kRadixBits)
+      return fail(ONESWEEP_ERROR_UNSUPPORTED, "digit_bits %d not built (only 8)", cfg->digit_bits);
+    if (cfg->block_threads != 0) r->shape.block = cfg->block_threads;
+    if (cfg->items_per_thread != 0) r->shape.ipt = cfg->items_per_thread;
+    if (cfg->hist_blocks_per_cu < 0 || cfg->hist_blocks_per_cu > 64)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "hist_blocks_per_cu %d out of [0, 64]",
+                  cfg->hist_blocks_per_cu);
+    if (cfg->hist_blocks_per_cu != 0) r->hist_blocks_per_cu = cfg->hist_blocks_per_cu;
+    r->trace = cfg->trace;
+    if (r->trace && (r->trace->capacity < 0 || r->trace->capacity > ONESWEEP_TRACE_MAX ||
+                     (r->trace->capacity > 0 && r->trace->events == nullptr)))
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "trace capacity/events invalid");
+  }
+  if (!binning_shape_supported(r->shape))
+    return fail(ONESWEEP_ERROR_UNSUPPORTED,
+                "binning shape (key_bits=%d, values=%d, block=%d, items=%d) not built", key_bits,
+                (int)has_values, r->shape.block, r->shape.ipt);
+  return ONESWEEP_SUCCESS;
+}
+
+// Temporary storage of a full sort. The cleared region (histograms, tile
+// counters, status words) is contiguous so one kernel clears it.
+struct SortLayout {
+  size_t hist, counters, status, zero_end;
+  size_t offsets, plan, tmp_keys, tmp_vals, total;
+  uint32_t tiles;
+  size_t status_words_per_place;
+};
+
+SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size_t tile) {
+  SortLayout L{};
+  L.tiles = static_cast<uint32_t>((n + tile - 1) / tile);
+  L.status_words_per_place = static_cast<size_t>(L.tiles) * kRadix;
+  size_t off = 0;
+  L.hist = off;
+  off += align_up(sizeof(uint32_t) * kMaxPlaces * kRadix);
+  L.counters = off;
+  off += kAlign;
+  L.status = off;
+  off += align_up(sizeof(uint32_t) * L.status_words_per_place * places);
+  L.zero_end = off;
+  L.offsets = off;
+  off += align_up(sizeof(uint32_t) * kMaxPlaces * kRadix);
+  L.plan = off;
+  off += kAlign;
+  L.tmp_keys = off;
+  off += align_up(n * (key_bits / 8));
+  L.tmp_vals = off;
+  if (has_values) off += align_up(n * sizeof(uint32_t));
+  L.total = off;
+  return L;
+}
+
+bool ranges_overlap(const void *a, size_t abytes, const void *b, size_t bbytes) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+// Records events around launches when tracing is on.
+struct Tracer {
+  onesweep_trace_t *t;
+  hipStream_t stream;
+  int next = 0;
+  Tracer(onesweep_trace_t *tr, hipStream_t s) : t(tr), stream(s) {
+    if (t) t->count = 0;
+  }
+  hipError_t before(int kind) {
+    if (!t || next >= t->capacity) return hipSuccess;
+    t->kinds[next] = kind;
+    return hipEventRecord(static_cast<hipEvent_t>(t->events[2 * next]), stream);
+  }
+  hipError_t after() {
+    if (!t || next >= t->capacity) return hipSuccess;
+    hipError_t e = hipEventRecord(static_cast<hipEvent_t>(t->events[2 * next + 1]), stream);
+    ++next;
+    t->count = next;
+    return e;
+  }
+};
+
+#define ONESWEEP_LAUNCH(tracer, kind, what, expr)          \
+  do {                                                     \
+    hipError_t e_ = (tracer).before(kind);                 \
+    if (e_ == hipSuccess) e_ = (expr);                     \
+    if (e_ == hipSuccess) e_ = (tracer).after();           \
+    if (e_ != hipSuccess) return hip_fail(e_, what);       \
+  } while (0)
+
+onesweep_status_t check_common(size_t *temp_bytes, size_t n, int key_bits, int begin_bit,
+                               int end_bit) {
+  if (temp_bytes == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp_bytes is NULL");
+  if (key_bits != 32 && key_bits != 64)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "key_bits %d is not 32 or 64", key_bits);
+  if (begin_bit < 0 || begin_bit > end_bit || end_bit > key_bits)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "bit range [%d, %d) invalid for %d-bit keys",
+                begin_bit, end_bit, key_bits);
+  if (n >= kMaxN)
+    return fail(ONESWEEP_ERROR_TOO_LARGE, "n = %zu is not below 2^30", n);
+  return ONESWEEP_SUCCESS;
+}
+
+onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_in,
+                            void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                            bool has_values, size_t n, int key_bits, int begin_bit, int end_bit,
+                            const onesweep_config_t *cfg, hipStream_t stream) {
+  g_error[0] = '\0';
+  onesweep_status_t st = check_common(temp_bytes, n, key_bits, begin_bit, end_bit);
+  if (st) return st;
+  Resolved rc;
+  if ((st = resolve(key_bits, has_values, cfg, &rc))) return st;
+  const int places = num_places(begin_bit, end_bit);
+  const size_t tile = static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
+  const SortLayout L = sort_layout(n, key_bits, has_values, places, tile);
+  if (d_temp == nullptr) {
+    *temp_bytes = L.total;
+    return ONESWEEP_SUCCESS;
+  }
+  if (rc.trace) rc.trace->count = 0;
+  if (n == 0) return ONESWEEP_SUCCESS;
+  if (*temp_bytes < L.total)
+    return fail(ONESWEEP_ERROR_INSUFFICIENT_TEMP, "temp storage %zu bytes, need %zu",
+                *temp_bytes, L.total);
+  const size_t kb = static_cast<size_t>(key_bits / 8);
+  if (!keys_in || !keys_out) return fail(ONESWEEP_ERROR_INVALID_VALUE, "NULL key pointer");
+  if (has_values && (!vals_in || !vals_out))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "NULL value pointer");
+  if ((reinterpret_cast<uintptr_t>(d_temp) & (kAlign - 1)) != 0)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_temp is not 256-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(keys_in) | reinterpret_cast<uintptr_t>(keys_out)) & (kb - 1))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "key pointers not %zu-byte aligned", kb);
+  if (has_values &&
+      ((reinterpret_cast<uintptr_t>(vals_in) | reinterpret_cast<uintptr_t>(vals_out)) & 3u))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "value pointers not 4-byte aligned");
+  const bool keys_alias = keys_in == keys_out;
+  if (!keys_alias && ranges_overlap(keys_in, n * kb, keys_out, n * kb))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "key input and output partially overlap");
+  bool vals_alias = false;
+  if (has_values) {
+    vals_alias = vals_in == vals_out;
+    if (!vals_alias && ranges_overlap(vals_in, n * 4, vals_out, n * 4))
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "value input and output partially overlap");
+    if (ranges_overlap(keys_in, n * kb, vals_out, n * 4) ||
+        ranges_overlap(keys_out, n * kb, vals_in, n * 4) ||
+        ranges_overlap(keys_out, n * kb, vals_out, n * 4))
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "key and value buffers overlap");
+  }
+  if (ranges_overlap(d_temp, L.total, keys_in, n * kb) ||
+      ranges_overlap(d_temp, L.total, keys_out, n * kb) ||
+      (has_values && (ranges_overlap(d_temp, L.total, vals_in, n * 4) ||
+                      ranges_overlap(d_temp, L.total, vals_out, n * 4))))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp storage overlaps keys or values");
+  const bool alias = keys_alias || vals_alias;
+
+  int cus = 0;
+  if ((st = device_cus(&cus))) return st;
+  const uint32_t stream_grid = static_cast<uint32_t>(cus) * 4u;
+  Tracer tr(rc.trace, stream);
+  char *temp = static_cast<char *>(d_temp);
+
+  CopyArgs ca{};
+  ca.keys[kBufIn] = const_cast<void *>(keys_in);
+  ca.keys[kBufOut] = keys_out;
+  ca.keys[kBufTmp] = temp + L.tmp_keys;
+  ca.vals[kBufIn] = const_cast<uint32_t *>(vals_in);
+  ca.vals[kBufOut] = vals_out;
+  ca.vals[kBufTmp] = has_values ? reinterpret_cast<uint32_t *>(temp + L.tmp_vals) : nullptr;
+  ca.n = static_cast<uint32_t>(n);
+  ca.key_bytes = static_cast<int>(kb);
+
+  if (places == 0) {  // empty bit range: the sorted order is the input order
+    ca.plan = nullptr;
+    if (!alias || (has_values && keys_alias != vals_alias))
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_COPY, "copy", launch_copy(ca, stream_grid, stream));
+    return ONESWEEP_SUCCESS;
+  }
+
+  uint32_t *hist = reinterpret_cast<uint32_t *>(temp + L.hist);
+  uint32_t *counters = reinterpret_cast<uint32_t *>(temp + L.counters);
+  uint32_t *status = reinterpret_cast<uint32_t *>(temp + L.status);
+  uint32_t *offsets = reinterpret_cast<uint32_t *>(temp + L.offsets);
+  PassPlan *plan = reinterpret_cast<PassPlan *>(temp + L.plan);
+
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "clear",
+                  launch_fill_zero(temp + L.hist, L.zero_end - L.hist, stream_grid, stream));
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
+                  launch_histogram(key_bits, keys_in, hist, static_cast<uint32_t>(n), begin_bit,
+                                   end_bit, places,
+                                   static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), stream));
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_SCAN, "scan",
+                  launch_scan(hist, offsets, plan, places, static_cast<uint32_t>(n), alias,
+                              stream));
+  for (int j = 0; j < places; ++j) {
+    const int lo = begin_bit + j * kRadixBits;
+    const int width = (lo + kRadixBits <= end_bit) ? kRadixBits : end_bit - lo;
+    if (key_bits == 32) {
+      BinningArgs<uint32_t> a{};
+      for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<uint32_t *>(ca.keys[b]);
+      for (int b = 0; b < 3; ++b) a.vals[b] = ca.vals[b];
+      a.bin_offsets = offsets + j * kRadix;
+      a.status = status + j * L.status_words_per_place;
+      a.tile_counter = counters + j;
+      a.plan = plan;
+      a.n = static_cast<uint32_t>(n);
+      a.place = j;
+      a.shift = lo;
+      a.width = width;
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
+                      launch_binning(rc.shape, &a, L.tiles, stream));
+    } else {
+      BinningArgs<uint64_t> a{};
+      for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<uint64_t *>(ca.keys[b]);
+      for (int b = 0; b < 3; ++b) a.vals[b] = ca.vals[b];
+      a.bin_offsets = offsets + j * kRadix;
+      a.status = status + j * L.status_words_per_place;
+      a.tile_counter = counters + j;
+      a.plan = plan;
+      a.n = static_cast<uint32_t>(n);
+      a.place = j;
+      a.shift = lo;
+      a.width = width;
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
+                      launch_binning(rc.shape, &a, L.tiles, stream));
+    }
+  }
+  ca.plan = plan;
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_COPY, "copy", launch_copy(ca, stream_grid, stream));
+  return ONESWEEP_SUCCESS;
+}
+
+}  // namespace
+}  // namespace onesweep
+
+using namespace onesweep;
+
+extern "C" {
+
+onesweep_status_t onesweep_sort_keys(void *d_temp, size_t *temp_bytes, const void *d_keys_in,
+                                     void *d_keys_out, size_t n, int key_bits, int begin_bit,
+                                     int end_bit, int stable, const onesweep_config_t *cfg,
+                                     onesweep_stream_t stream) {
+  (void)stable;
+  return sort_impl(d_temp, temp_bytes, d_keys_in, d_keys_out, nullptr, nullptr, false, n,
+                   key_bits, begin_bit, end_bit, cfg, reinterpret_cast<hipStream_t>(stream));
+}
+
+onesweep_status_t onesweep_sort_pairs(void *d_temp, size_t *temp_bytes, const void *d_keys_in,
+                                      void *d_keys_out, const uint32_t *d_vals_in,
+                                      uint32_t *d_vals_out, size_t n, int key_bits,
+                                      int begin_bit, int end_bit, int stable,
+                                      const onesweep_config_t *cfg, onesweep_stream_t stream) {
+  (void)stable;
+  return sort_impl(d_temp, temp_bytes, d_keys_in, d_keys_out, d_vals_in, d_vals_out, true, n,
+                   key_bits, begin_bit, end_bit, cfg, reinterpret_cast<hipStream_t>(stream));
+}
+
+onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits, int begin_bit,
+                                     int end_bit, uint32_t *d_hist,
+                                     const onesweep_config_t *cfg, onesweep_stream_t stream) {
+  g_error[0] = '\0';
+  size_t dummy = 0;
+  onesweep_status_t st = check_common(&dummy, n, key_bits, begin_bit, end_bit);
+  if (st) return st;
+  Resolved rc;
+  if ((st = resolve(key_bits, false, cfg, &rc))) return st;
+  const int places = num_places(begin_bit, end_bit);
+  if (places == 0) return ONESWEEP_SUCCESS;
+  if (!d_hist) return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_hist is NULL");
+  if (n > 0 && !d_keys) return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_keys is NULL");
+  if (reinterpret_cast<uintptr_t>(d_keys) & (key_bits / 8 - 1))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_keys not aligned to the key size");
+  if (reinterpret_cast<uintptr_t>(d_hist) & 3u)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_hist not 4-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int cus = 0;
+  if ((st = device_cus(&cus))) return st;
+  Tracer tr(rc.trace, s);
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "clear",
+                  launch_fill_zero(d_hist, sizeof(uint32_t) * places * kRadix, 1, s));
+  if (n == 0) return ONESWEEP_SUCCESS;
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
+                  launch_histogram(key_bits, d_keys, d_hist, static_cast<uint32_t>(n), begin_bit,
+                                   end_bit, places,
+                                   static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), s));
+  return ONESWEEP_SUCCESS;
+}
+
+onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
+                                        const void *d_src_keys, void *d_dst_keys,
+                                        const uint32_t *d_src_vals, uint32_t *d_dst_vals,
+                                        size_t n, int key_bits, int shift, int width,
+                                        const uint32_t *d_bin_offsets,
+                                        const onesweep_config_t *cfg,
+                                        onesweep_stream_t stream) {
+  g_error[0] = '\0';
+  if (temp_bytes == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp_bytes is NULL");
+  if (key_bits != 32 && key_bits != 64)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "key_bits %d is not 32 or 64", key_bits);
+  if (width < 1 || width > kRadixBits || shift < 0 || shift + width > key_bits)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "digit bits [%d, %d) invalid", shift,
+                shift + width);
+  if (n >= kMaxN) return fail(ONESWEEP_ERROR_TOO_LARGE, "n = %zu is not below 2^30", n);
+  const bool has_values = d_src_vals != nullptr || d_dst_vals != nullptr;
+  Resolved rc;
+  onesweep_status_t st;
+  if ((st = resolve(key_bits, has_values, cfg, &rc))) return st;
+  const size_t tile = static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
+  const uint32_t tiles = static_cast<uint32_t>((n + tile - 1) / tile);
+  const size_t need = kAlign + align_up(sizeof(uint32_t) * kRadix * static_cast<size_t>(tiles));
+  if (d_temp == nullptr) {
+    *temp_bytes = need;
+    return ONESWEEP_SUCCESS;
+  }
+  if (rc.trace) rc.trace->count = 0;
+  if (n == 0) return ONESWEEP_SUCCESS;
+  if (*temp_bytes < need)
+    return fail(ONESWEEP_ERROR_INSUFFICIENT_TEMP, "temp storage %zu bytes, need %zu",
+                *temp_bytes, need);
+  const size_t kb = static_cast<size_t>(key_bits / 8);
+  if (!d_src_keys || !d_dst_keys || !d_bin_offsets)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "NULL pointer");
+  if (has_values && (!d_src_vals || !d_dst_vals))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "only one value pointer given");
+  if ((reinterpret_cast<uintptr_t>(d_temp) & (kAlign - 1)) != 0)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_temp is not 256-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(d_src_keys) | reinterpret_cast<uintptr_t>(d_dst_keys)) &
+      (kb - 1))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "key pointers not aligned");
+  if (ranges_overlap(d_src_keys, n * kb, d_dst_keys, n * kb) ||
+      (has_values && ranges_overlap(d_src_vals, n * 4, d_dst_vals, n * 4)))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "source and destination overlap");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int cus = 0;
+  if ((st = device_cus(&cus))) return st;
+  Tracer tr(rc.trace, s);
+  char *temp = static_cast<char *>(d_temp);
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "clear",
+                  launch_fill_zero(temp, need, static_cast<uint32_t>(cus) * 4u, s));
+  uint32_t *counter = reinterpret_cast<uint32_t *>(temp);
+  uint32_t *status = reinterpret_cast<uint32_t *>(temp + kAlign);
+  if (key_bits == 32) {
+    BinningArgs<uint32_t> a{};
+    a.keys[kBufIn] = static_cast<uint32_t *>(const_cast<void *>(d_src_keys));
+    a.keys[kBufOut] = static_cast<uint32_t *>(d_dst_keys);
+    a.vals[kBufIn] = const_cast<uint32_t *>(d_src_vals);
+    a.vals[kBufOut] = d_dst_vals;
+    a.bin_offsets = d_bin_offsets;
+    a.status = status;
+    a.tile_counter = counter;
+    a.plan = nullptr;
+    a.n = static_cast<uint32_t>(n);
+    a.place = 0;
+    a.shift = shift;
+    a.width = width;
+    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
+                    launch_binning(rc.shape, &a, tiles, s));
+  } else {
+    BinningArgs<uint64_t> a{};
+    a.keys[kBufIn] = static_cast<uint64_t *>(const_cast<void *>(d_src_keys));
+    a.keys[kBufOut] = static_cast<uint64_t *>(d_dst_keys);
+    a.vals[kBufIn] = const_cast<uint32_t *>(d_src_vals);
+    a.vals[kBufOut] = d_dst_vals;
+    a.bin_offsets = d_bin_offsets;
+    a.status = status;
+    a.tile_counter = counter;
+    a.plan = nullptr;
+    a.n = static_cast<uint32_t>(n);
+    a.place = 0;
+    a.shift = shift;
+    a.width = width;
+    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
+                    launch_binning(rc.shape, &a, tiles, s));
+  }
+  return ONESWEEP_SUCCESS;
+}
+
+size_t onesweep_tile_items(int key_bits, int has_values, const onesweep_config_t *cfg) {
+  if (key_bits != 32 && key_bits != 64) return 0;
+  Resolved rc;
+  if (resolve(key_bits, has_values != 0, cfg, &rc) != ONESWEEP_SUCCESS) return 0;
+  return static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
+}
+
+const char *onesweep_last_error(void) { return g_error; }
+
+const char *onesweep_version(void) { return "onesweep-gfx950 0.1"; }
+
+}  // extern "C"

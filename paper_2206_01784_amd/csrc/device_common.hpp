@@ -1,0 +1,92 @@
+// Shared device-side definitions of the Onesweep kernels for gfx950 (CDNA4,
+// wave64). Included by every kernel translation unit; host-only code uses
+// internal.hpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace onesweep {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;  // r = 256 bins per digit place
+constexpr int kMaxPlaces = 8;            // 64-bit keys with 8-bit digits
+constexpr int kWave = 64;
+
+// Chained-scan status word (Section 3, Figure 6): 2-bit status above a
+// 30-bit value. N = not ready, L = tile-local count, G = inclusive prefix.
+constexpr uint32_t kValueMask = (1u << 30) - 1u;
+constexpr uint32_t kFlagMask = 3u << 30;
+constexpr uint32_t kFlagL = 1u << 30;
+constexpr uint32_t kFlagG = 2u << 30;
+
+// Buffer ids used by the pass plan.
+enum : uint32_t { kBufIn = 0, kBufOut = 1, kBufTmp = 2, kNoBuffer = 3 };
+
+// The pass plan is computed on the device by the scan kernel from the exact
+// histograms, so the host never synchronises to learn which passes run:
+// a place whose histogram puts all n keys in one bin is an identity
+// permutation and is skipped; executed passes alternate buffers so that the
+// last one lands in the output.
+struct PassPlan {
+  uint32_t run[kMaxPlaces];
+  uint32_t src[kMaxPlaces];
+  uint32_t dst[kMaxPlaces];
+  uint32_t copy_src;  // buffer copied into the output at the end, or kNoBuffer
+  uint32_t executed;
+  uint32_t pad[14];
+};
+static_assert(sizeof(PassPlan) <= 256, "plan fits one 256-byte slot");
+
+template <typename K>
+struct BinningArgs {
+  K *keys[3];                  // in, out, tmp (in is only read)
+  uint32_t *vals[3];           // same ids; unused for keys-only
+  const uint32_t *bin_offsets; // 256 global bin offsets of this place
+  uint32_t *status;            // [tiles][256] status words of this place
+  uint32_t *tile_counter;      // dynamic tile ids of this place
+  const PassPlan *plan;        // NULL: run unconditionally in -> out
+  uint32_t n;
+  int place;
+  int shift;
+  int width;
+};
+
+template <typename K>
+struct HistogramArgs {
+  const K *keys;
+  uint32_t *hist;  // [places][256], cleared before launch
+  uint32_t n;
+  int begin_bit;
+  int end_bit;
+  int places;
+};
+
+// Agent-scope atomics: successive tiles usually run on different XCDs, whose
+// L2 caches are not coherent with each other, so status words and tile
+// counters go through device-coherent accesses. A status word carries its own
+// value, so relaxed ordering is enough for the look-back protocol.
+__device__ __forceinline__ void store_status(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_status(const uint32_t *p) {
+  return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of `mask` in lanes below the calling lane.
+__device__ __forceinline__ uint32_t count_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
+  return static_cast<uint32_t>(key >> shift) & mask;
+}
+
+}  // namespace onesweep

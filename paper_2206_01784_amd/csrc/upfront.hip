@@ -1,0 +1,228 @@
+// Phases 1 and 2 of Onesweep (Section 3, "Upfront histogram kernel" and
+// "Exclusive sum kernel", Figure 5), plus the small support kernels (clear,
+// copy) that keep the launch sequence free of memset/memcpy nodes.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace onesweep {
+
+// ---------------------------------------------------------------- histogram
+//
+// A persistent grid (a fixed number of workgroups per CU) walks the keys in
+// tile-cyclic order. Every workgroup counts into private LDS histograms with
+// LDS atomics and, once its tiles are consumed, adds them to the global
+// histograms with global atomics. Counts depend only on the multiset of keys,
+// so one read of the keys yields the histograms of every digit place.
+//
+// kCopies interleaved copies of each counter (copy = lane % kCopies, copy
+// index fastest) keep lanes that share a digit on different LDS banks, which
+// bounds the serialisation of skewed inputs (all-equal keys) to
+// 64 / kCopies-way.
+template <typename K, int kBlock, int kVec, int kCopies>
+__global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
+  constexpr int kMaxP = static_cast<int>(sizeof(K));  // 8-bit places in the key
+  constexpr int kPerVec = 16 / static_cast<int>(sizeof(K));
+  constexpr int kTile = kBlock * kVec * kPerVec;
+  __shared__ uint32_t s_hist[kMaxP * kRadix * kCopies];
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kMaxP * kRadix * kCopies; i += kBlock) s_hist[i] = 0u;
+
+  int shifts[kMaxP];
+  uint32_t masks[kMaxP];
+#pragma unroll
+  for (int j = 0; j < kMaxP; ++j) {
+    const int lo = a.begin_bit + j * kRadixBits;
+    const int hi = min(lo + kRadixBits, a.end_bit);
+    shifts[j] = lo < 64 ? lo : 0;
+    masks[j] = (j < a.places) ? ((1u << (hi - lo)) - 1u) : 0u;
+  }
+  const int places = a.places;
+  uint32_t *my_hist = s_hist + (tid % kCopies);
+  __syncthreads();
+
+  auto count_key = [&](K k) {
+#pragma unroll
+    for (int j = 0; j < kMaxP; ++j) {
+      if (j < places) {
+        const uint32_t d = static_cast<uint32_t>(k >> shifts[j]) & masks[j];
+        atomicAdd(&my_hist[(j * kRadix + d) * kCopies], 1u);
+      }
+    }
+  };
+
+  const uint32_t n = a.n;
+  const bool aligned = (reinterpret_cast<uintptr_t>(a.keys) & 15u) == 0u;
+  for (uint32_t base = blockIdx.x * kTile; base < n; base += gridDim.x * kTile) {
+    if (aligned && base + kTile <= n) {
+      const uint4 *v = reinterpret_cast<const uint4 *>(a.keys + base);
+      uint4 q[kVec];
+#pragma unroll
+      for (int i = 0; i < kVec; ++i) q[i] = v[i * kBlock + tid];
+#pragma unroll
+      for (int i = 0; i < kVec; ++i) {
+        if constexpr (sizeof(K) == 4) {
+          count_key(q[i].x);
+          count_key(q[i].y);
+          count_key(q[i].z);
+          count_key(q[i].w);
+        } else {
+          count_key(static_cast<K>(q[i].x) | (static_cast<K>(q[i].y) << 32));
+          count_key(static_cast<K>(q[i].z) | (static_cast<K>(q[i].w) << 32));
+        }
+      }
+    } else {
+      const uint32_t end = min(n, base + static_cast<uint32_t>(kTile));
+      for (uint32_t i = base + tid; i < end; i += kBlock) count_key(a.keys[i]);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < places * kRadix; i += kBlock) {
+    uint32_t sum = 0u;
+#pragma unroll
+    for (int c = 0; c < kCopies; ++c) sum += s_hist[i * kCopies + c];
+    if (sum != 0u) atomicAdd(&a.hist[i], sum);
+  }
+}
+
+constexpr int kHistVec = 4;     // uint4 loads per thread per tile
+constexpr int kHistCopies = 8;  // interleaved LDS copies per counter
+
+hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint32_t n,
+                            int begin_bit, int end_bit, int places, uint32_t grid,
+                            hipStream_t stream) {
+  if (key_bits == 32) {
+    HistogramArgs<uint32_t> a{static_cast<const uint32_t *>(keys), hist, n, begin_bit, end_bit,
+                              places};
+    hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies>),
+                       dim3(grid), dim3(kHistBlock), 0, stream, a);
+  } else {
+    HistogramArgs<uint64_t> a{static_cast<const uint64_t *>(keys), hist, n, begin_bit, end_bit,
+                              places};
+    hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies>),
+                       dim3(grid), dim3(kHistBlock), 0, stream, a);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- exclusive sums + plan
+//
+// One workgroup of 256 threads: thread v owns digit v of every place. Besides
+// the global bin offsets, it marks a place trivial when one bin holds all n
+// keys (the pass would be the identity permutation) and lays out the buffer
+// route of the executed passes.
+__global__ void __launch_bounds__(kRadix) scan_kernel(const uint32_t *hist, uint32_t *offsets,
+                                                      PassPlan *plan, int places, uint32_t n,
+                                                      int alias) {
+  __shared__ uint32_t s_wave_sum[kRadix / kWave];
+  __shared__ uint32_t s_run[kMaxPlaces];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  for (int j = 0; j < places; ++j) {
+    const uint32_t h = hist[j * kRadix + tid];
+    uint32_t incl = h;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl += t;
+    }
+    if (lane == kWave - 1) s_wave_sum[wave] = incl;
+    const int trivial = __syncthreads_or(h == n);
+    uint32_t excl = incl - h;
+    for (int w = 0; w < wave; ++w) excl += s_wave_sum[w];
+    offsets[j * kRadix + tid] = excl;
+    if (tid == 0) s_run[j] = trivial ? 0u : 1u;
+    __syncthreads();  // s_wave_sum is reused by the next place
+  }
+  if (tid == 0) {
+    PassPlan p;
+    uint32_t executed = 0;
+    for (int j = 0; j < places; ++j) executed += s_run[j];
+    uint32_t cur = kBufIn, k = 0;
+    for (int j = 0; j < kMaxPlaces; ++j) {
+      p.run[j] = 0u;
+      p.src[j] = kBufIn;
+      p.dst[j] = kBufOut;
+      if (j < places && s_run[j]) {
+        ++k;
+        uint32_t to;
+        if (alias)  // input == output: the first pass must not write in place
+          to = (k & 1u) ? kBufTmp : kBufOut;
+        else        // the last executed pass writes the output
+          to = ((executed - k) & 1u) ? kBufTmp : kBufOut;
+        p.run[j] = 1u;
+        p.src[j] = cur;
+        p.dst[j] = to;
+        cur = to;
+      }
+    }
+    p.executed = executed;
+    if (executed == 0u)
+      p.copy_src = alias ? kNoBuffer : kBufIn;
+    else
+      p.copy_src = (cur == kBufOut) ? kNoBuffer : cur;
+    for (int i = 0; i < 14; ++i) p.pad[i] = 0u;
+    *plan = p;
+  }
+}
+
+hipError_t launch_scan(const uint32_t *hist, uint32_t *offsets, PassPlan *plan, int places,
+                       uint32_t n, bool alias, hipStream_t stream) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kRadix), 0, stream, hist, offsets, plan, places,
+                     n, alias ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- copy
+__global__ void __launch_bounds__(256) copy_kernel(CopyArgs a) {
+  uint32_t from = kBufIn;
+  if (a.plan != nullptr) {
+    from = a.plan->copy_src;
+    if (from == kNoBuffer) return;
+  }
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  const size_t first = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  auto copy_bytes = [&](const void *s, void *d, size_t bytes) {
+    if (s == d) return;
+    const bool vec = ((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(d)) & 15u) == 0u;
+    size_t done = 0;
+    if (vec) {
+      const size_t nv = bytes / 16;
+      const uint4 *sv = static_cast<const uint4 *>(s);
+      uint4 *dv = static_cast<uint4 *>(d);
+      for (size_t i = first; i < nv; i += stride) dv[i] = sv[i];
+      done = nv * 16;
+    }
+    const uint32_t *sw = static_cast<const uint32_t *>(s);
+    uint32_t *dw = static_cast<uint32_t *>(d);
+    for (size_t i = done / 4 + first; i < bytes / 4; i += stride) dw[i] = sw[i];
+  };
+  copy_bytes(a.keys[from], a.keys[kBufOut], static_cast<size_t>(a.n) * a.key_bytes);
+  if (a.vals[from] != nullptr && a.vals[kBufOut] != nullptr)
+    copy_bytes(a.vals[from], a.vals[kBufOut], static_cast<size_t>(a.n) * 4u);
+}
+
+hipError_t launch_copy(const CopyArgs &a, uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- clear
+__global__ void __launch_bounds__(256) fill_zero_kernel(uint32_t *p, size_t words) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  const size_t first = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t nv = (reinterpret_cast<uintptr_t>(p) & 15u) == 0u ? words / 4 : 0;
+  uint4 *pv = reinterpret_cast<uint4 *>(p);
+  for (size_t i = first; i < nv; i += stride) pv[i] = make_uint4(0u, 0u, 0u, 0u);
+  for (size_t i = nv * 4 + first; i < words; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, uint32_t grid, hipStream_t stream) {
+  if (bytes == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(256), 0, stream,
+                     static_cast<uint32_t *>(p), bytes / 4);
+  return hipGetLastError();
+}
+
+}  // namespace onesweep

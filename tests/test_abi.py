@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates arguments before touching any GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "onesweep.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(onesweep_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("onesweep_sort_keys", "onesweep_sort_pairs", "onesweep_histogram",
+              "onesweep_binning_pass", "onesweep_last_error"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_library_is_built_for_gfx950_only():
+    """The offload bundle ids in the library name gfx950 and no other target."""
+    import paper_2206_01784_amd as ow
+    blob = open(ow.LIB_PATH, "rb").read()
+    targets = set(re.findall(rb"amdgcn-amd-amdhsa--(gfx[0-9a-z]+)", blob))
+    assert targets == {b"gfx950"}, targets
+
+
+def test_temp_size_query_needs_no_gpu():
+    import paper_2206_01784_amd as ow
+    t = ow.tile_items(32)
+    n = 1 << 28
+    need = ow.sort_temp_bytes(n, 32)
+    # at least the ping-pong buffer plus p * tiles * 256 status words
+    assert need >= 4 * n + 4 * (-(-n // t)) * 256 * 4
+    assert ow.sort_temp_bytes(1 << 20, 64, True) >= (1 << 20) * 12
+    assert ow.sort_temp_bytes(0, 32) > 0
+
+
+@pytest.mark.parametrize("kwargs,code", [
+    (dict(key_bits=48), 1),
+    (dict(begin_bit=9, end_bit=8), 1),
+    (dict(end_bit=33), 1),
+    (dict(n=1 << 30), 2),
+])
+def test_invalid_arguments_are_rejected_on_the_host(kwargs, code):
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    args = dict(n=100, key_bits=32, begin_bit=0, end_bit=32)
+    args.update(kwargs)
+    size = ctypes.c_size_t(0)
+    rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, args["n"], args["key_bits"],
+                                args["begin_bit"], args["end_bit"], 1, None, None)
+    assert rc == code
+    assert lib.onesweep_last_error()
+
+
+def test_unsupported_config_is_rejected():
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    size = ctypes.c_size_t(0)
+    cfg = ow.make_config(block_threads=384, items_per_thread=7)
+    rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
+                                ctypes.byref(cfg), None)
+    assert rc == ow.ERROR_UNSUPPORTED
+    assert ow.tile_items(32, False, cfg) == 0
+    cfg = ow.make_config(digit_bits=7)
+    rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
+                                ctypes.byref(cfg), None)
+    assert rc == ow.ERROR_UNSUPPORTED
+
+
+def test_insufficient_temp_and_null_pointers():
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    size = ctypes.c_size_t(10)
+    rc = lib.onesweep_sort_keys(ctypes.c_void_p(256), ctypes.byref(size), ctypes.c_void_p(4096),
+                                ctypes.c_void_p(8192), 100, 32, 0, 32, 1, None, None)
+    assert rc == ow.ERROR_INSUFFICIENT_TEMP
+    need = ow.sort_temp_bytes(100)
+    size = ctypes.c_size_t(need)
+    rc = lib.onesweep_sort_keys(ctypes.c_void_p(256), ctypes.byref(size), None,
+                                ctypes.c_void_p(8192), 100, 32, 0, 32, 1, None, None)
+    assert rc == ow.ERROR_INVALID_VALUE
+    # partial overlap of input and output
+    rc = lib.onesweep_sort_keys(ctypes.c_void_p(1 << 20), ctypes.byref(size),
+                                ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 64), 100, 32, 0, 32,
+                                1, None, None)
+    assert rc == ow.ERROR_INVALID_VALUE
+    # misaligned temp
+    rc = lib.onesweep_sort_keys(ctypes.c_void_p((1 << 20) + 4), ctypes.byref(size),
+                                ctypes.c_void_p(4096), ctypes.c_void_p(65536), 100, 32, 0, 32, 1,
+                                None, None)
+    assert rc == ow.ERROR_INVALID_VALUE
+
+
+def test_empty_input_accepts_null_pointers():
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    size = ctypes.c_size_t(0)
+    assert lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 0, 32, 0, 32, 1, None,
+                                  None) == 0
+    assert lib.onesweep_sort_keys(ctypes.c_void_p(256), ctypes.byref(size), None, None, 0, 32, 0,
+                                  32, 1, None, None) == 0

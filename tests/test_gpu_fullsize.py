@@ -1,0 +1,80 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration the
+benchmark times (default config): 2^28 uint32 keys (uniform, AND-of-4, all
+equal), 2^28 uint32 pairs and 2^27 uint64-key pairs, values = original index.
+
+The oracle runs at full size for the uniform cases (bit-exact comparison of
+every element); the skewed cases are checked through properties that fix the
+result at any size (sorted, oracle histograms of every place, multiset sums)
+plus order statistics the oracle-side numpy computes one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+N28 = 1 << 28
+
+
+@pytest.fixture(scope="module")
+def ow():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2206_01784_amd as mod
+    return mod
+
+
+def sorted_on_gpu(t):
+    x = t.to(torch.int64) if t.dtype == torch.uint32 else t.view(torch.int64) ^ (-(1 << 63))
+    ok = bool((x[1:] >= x[:-1]).all())
+    del x
+    return ok
+
+
+def test_full_u32_keys_uniform(ow):
+    keys = W.uniform(2, N28)
+    t = torch.from_numpy(keys).cuda()
+    out = ow.sort_keys(t)
+    want, _ = oracle.sort(keys)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("dist", ["and4", "equal"])
+def test_full_u32_keys_skewed(ow, dist):
+    keys = W.and_of_q(2, 4, N28) if dist == "and4" else W.all_equal(2, N28)
+    t = torch.from_numpy(keys).cuda()
+    out = ow.sort_keys(t)
+    torch.cuda.synchronize()
+    assert sorted_on_gpu(out)
+    o = out.cpu().numpy()
+    assert np.array_equal(oracle.histograms(o), oracle.histograms(keys))
+    assert int(o.astype(np.uint64).sum()) == int(keys.astype(np.uint64).sum())
+    assert int(np.bitwise_xor.reduce(o)) == int(np.bitwise_xor.reduce(keys))
+    rng = np.random.default_rng(0)
+    for i in rng.integers(0, N28, 8):
+        v = o[i]
+        lt = int(np.count_nonzero(keys < v))
+        le = lt + int(np.count_nonzero(keys == v))
+        assert lt <= i < le
+
+
+def test_full_u32_pairs(ow):
+    keys = W.uniform(3, N28)
+    vals = np.arange(N28, dtype=np.uint32)
+    ko, vo = ow.sort_pairs(torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda())
+    wk, wv = oracle.sort(keys, vals)
+    assert np.array_equal(ko.cpu().numpy(), wk)
+    assert np.array_equal(vo.cpu().numpy(), wv)
+
+
+def test_full_u64_pairs(ow):
+    n = 1 << 27
+    keys = W.uniform(3, n, 64)
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = ow.sort_pairs(torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda())
+    wk, wv = oracle.sort(keys, vals)
+    assert np.array_equal(ko.cpu().numpy(), wk)
+    assert np.array_equal(vo.cpu().numpy(), wv)

@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle.
+
+Integer work, so the bar is bit-exact everywhere. Inputs come from the seeded
+generators in `workload`; expected values come only from `oracle`.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ow():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2206_01784_amd as mod
+    return mod
+
+
+def dev(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy()
+
+
+def keys_of(dist, seed, n, kb):
+    if dist == "uniform":
+        return W.uniform(seed, n, kb)
+    return W.make_keys(dist, seed, n, kb)
+
+
+# ------------------------------------------------------------------ phase 1
+
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("dist", ["uniform", "and4", "equal", "distinct16"])
+@pytest.mark.parametrize("n", [1, 1000, 3 * 4096 + 5, (1 << 20) + 123])
+def test_histogram_parity(ow, kb, dist, n):
+    keys = keys_of(dist, 31, n, kb)
+    for begin, end in [(0, kb), (3, kb - 5), (kb - 8, kb), (4, 9)]:
+        got = host(ow.histogram(dev(keys), begin, end)).astype(np.uint64)
+        want = oracle.histograms(keys, begin, end, 8)
+        assert np.array_equal(got, want), (dist, n, begin, end)
+
+
+def test_histogram_empty_and_unaligned(ow):
+    h = ow.histogram(torch.empty(0, dtype=torch.uint32, device="cuda"))
+    assert host(h).sum() == 0
+    keys = W.uniform(3, 10001)
+    t = dev(keys)
+    sub = t[1:]  # 4-byte aligned but not 16-byte aligned: scalar load path
+    assert np.array_equal(host(ow.histogram(sub)).astype(np.uint64),
+                          oracle.histograms(keys[1:], 0, 32, 8))
+
+
+# ------------------------------------------------------------------ phase 3 (one pass)
+
+SHAPES = {
+    (32, False): [(256, 16), (512, 16), (512, 12), (256, 24), (1024, 8)],
+    (32, True): [(256, 16), (512, 16), (512, 12), (256, 24)],
+    (64, False): [(256, 16), (512, 8), (512, 12)],
+    (64, True): [(256, 16), (512, 8), (512, 12)],
+}
+
+
+@pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
+def test_binning_pass_parity_and_final_status(ow, kb, vals):
+    for block, ipt in SHAPES[(kb, vals)]:
+        cfg = ow.make_config(block_threads=block, items_per_thread=ipt)
+        T = ow.tile_items(kb, vals, cfg)
+        assert T == block * ipt
+        for n in (1, T - 1, T, T + 1, 5 * T + 77):
+            keys = W.uniform(100 + n % 97, n, kb)
+            v = np.arange(n, dtype=np.uint32) if vals else None
+            for shift, width in ((0, 8), (kb - 8, 8), (5, 3)):
+                hist = oracle.histograms(keys, shift, shift + width, width)[0]
+                off = oracle.exclusive_sums(hist[None, :])[0]
+                off256 = np.zeros(256, dtype=np.uint32)
+                off256[:off.size] = off
+                off256[off.size:] = n
+                dk, dv, temp = ow.binning_pass(dev(keys), dev(off256), shift, width,
+                                               src_values=None if v is None else dev(v),
+                                               config=cfg)
+                wk, wv = oracle.binning_pass(keys, shift, width, off, v)
+                assert np.array_equal(host(dk), wk), (block, ipt, n, shift, width)
+                if vals:
+                    assert np.array_equal(host(dv), wv), (block, ipt, n, shift, width)
+                # The chained scan's final state (Figure 7f): every counter is G
+                # and holds the inclusive prefix of its digit over tiles.
+                g = -(-n // T)
+                st = host(temp[256:256 + g * 256 * 4].view(torch.uint32)).reshape(g, 256)
+                want = oracle.pass_status(keys, shift, width, T)
+                assert np.array_equal(st[:, :1 << width], want)
+                assert np.all(st[:, 1 << width:] == np.uint32(2 << 30))
+
+
+# ------------------------------------------------------------------ whole sorts
+
+def check_sort(ow, keys, vals, begin, end, cfg=None, inplace=False):
+    kb = 32 if keys.dtype == np.uint32 else 64
+    tk = dev(keys)
+    if vals is None:
+        out = tk if inplace else None
+        res = ow.sort_keys(tk, begin, end, out=out, config=cfg)
+        got_k, got_v = host(res), None
+    else:
+        tv = dev(vals)
+        rk, rv = ow.sort_pairs(tk, tv, begin, end, keys_out=tk if inplace else None,
+                               values_out=tv if inplace else None, config=cfg)
+        got_k, got_v = host(rk), host(rv)
+    wk, wv = oracle.sort(keys, vals, begin, end, 8)
+    assert np.array_equal(got_k, wk)
+    if vals is not None:
+        assert np.array_equal(got_v, wv)
+
+
+@pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
+def test_sort_every_shape_ragged_sizes(ow, kb, vals):
+    for block, ipt in SHAPES[(kb, vals)]:
+        cfg = ow.make_config(block_threads=block, items_per_thread=ipt)
+        T = block * ipt
+        for n in (2, T - 1, T + 1, 7 * T + 333):
+            keys = W.uniform(7 + n % 13, n, kb)
+            v = np.arange(n, dtype=np.uint32) if vals else None
+            check_sort(ow, keys, v, 0, kb, cfg)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("dist", ["and2", "and3", "and4", "equal", "zipf", "presorted",
+                                  "reverse", "distinct16"])
+def test_sort_distributions(ow, kb, dist):
+    n = 300001
+    keys = keys_of(dist, 17, n, kb)
+    check_sort(ow, keys, None, 0, kb)
+    check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_sort_partial_bit_ranges(ow, kb):
+    n = 123457
+    keys = W.uniform(5, n, kb)
+    vals = np.arange(n, dtype=np.uint32)
+    for begin, end in [(0, 1), (3, 11), (8, 16), (kb - 13, kb), (7, 7), (0, kb - 1), (1, kb)]:
+        check_sort(ow, keys, None, begin, end)
+        check_sort(ow, keys, vals, begin, end)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_sort_in_place(ow, kb):
+    n = 200003
+    keys = W.and_of_q(9, 2, n, kb)
+    check_sort(ow, keys, None, 0, kb, inplace=True)
+    check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb, inplace=True)
+    # skipped places change the parity of executed passes: 3 of 4 run here
+    k2 = (keys & np.array(0x00FFFFFF if kb == 32 else 0x00FFFFFFFFFFFFFF, dtype=keys.dtype))
+    check_sort(ow, k2, None, 0, kb, inplace=True)
+    check_sort(ow, k2, np.arange(n, dtype=np.uint32), 0, kb, inplace=True)
+    check_sort(ow, k2, None, 0, kb)
+
+
+def test_small_and_degenerate_sizes(ow):
+    for n in (0, 1, 2, 3, 63, 64, 65, 255, 256, 257, 4093):
+        for kb in (32, 64):
+            keys = W.uniform(n + 1, n, kb)
+            check_sort(ow, keys, None, 0, kb)
+            check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb)
+    two = np.array([5, 3] * 5000, dtype=np.uint32)
+    check_sort(ow, two, np.arange(two.size, dtype=np.uint32), 0, 32)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_one_million_uniform_u32_keys(ow, seed):
+    """2^20 uniform uint32 keys, 8-bit digits, 4 passes, bit-exact."""
+    keys = W.uniform(seed, 1 << 20)
+    check_sort(ow, keys, None, 0, 32)
+
+
+def test_trace_records_the_launch_sequence(ow):
+    n = 1 << 16
+    keys = dev(W.uniform(1, n))
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * 16)]
+    for e in events:
+        e.record()
+    torch.cuda.synchronize()
+    import ctypes
+    arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+    tr = ow.Trace()
+    tr.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    tr.capacity = 16
+    cfg = ow.make_config(trace=tr)
+    ow.sort_keys(keys, config=cfg)
+    torch.cuda.synchronize()
+    kinds = [tr.kinds[i] for i in range(tr.count)]
+    assert kinds == [ow.KERNEL_RESET, ow.KERNEL_HISTOGRAM, ow.KERNEL_SCAN] + \
+        [ow.KERNEL_BINNING] * 4 + [ow.KERNEL_COPY]
+    for i in range(tr.count):
+        assert events[2 * i].elapsed_time(events[2 * i + 1]) >= 0.0
+
+
+def test_graph_capture_replays(ow):
+    """Capture one sort into a HIP graph; replay with fresh inputs, with eager
+    work and synchronisation between replays; every replay must be exact."""
+    n = (1 << 18) + 7
+    static_in = torch.empty(n, dtype=torch.uint32, device="cuda")
+    static_out = torch.empty_like(static_in)
+    temp = torch.empty(ow.sort_temp_bytes(n), dtype=torch.uint8, device="cuda")
+    static_in.copy_(dev(W.uniform(1, n)))
+    ow.sort_keys(static_in, out=static_out, temp=temp)  # warm-up outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ow.sort_keys(static_in, out=static_out, temp=temp, stream=s)
+    torch.cuda.synchronize()
+    for seed in (11, 12, 13, 14):
+        keys = W.and_of_q(seed, 1 + seed % 3, n)
+        static_in.copy_(dev(keys))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(static_out), oracle.sort(keys)[0]), seed
+        # eager work between replays
+        eager = ow.sort_keys(dev(keys[: n // 2]))
+        torch.cuda.synchronize()
+        assert np.array_equal(host(eager), oracle.sort(keys[: n // 2])[0])

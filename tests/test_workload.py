@@ -17,7 +17,7 @@ def test_splitmix64_published_first_output():
 
 
 def test_vectorised_equals_scalar():
-    w = W.words(3, 1, 100, start=5)
+    w = W.words_numpy(3, 1, 100, start=5)
     b = int(W.base(3, 1))
     for i in range(100):
         z = (b + (i + 6) * 0x9E3779B97F4A7C15) & ((1 << 64) - 1)
@@ -95,3 +95,13 @@ def test_other_distributions():
     assert np.all(np.diff(W.presorted(1, 1000).astype(np.int64)) >= 0)
     assert np.all(np.diff(W.reverse_sorted(1, 1000).astype(np.int64)) <= 0)
     assert len(np.unique(W.distinct16(1, 10000))) <= 16
+
+
+def test_fast_generator_equals_numpy_definition():
+    for seed, stream, start, n in [(1, 1, 0, 5000), (3, 7, 123456, 999), (2, 200, 1 << 33, 64)]:
+        assert np.array_equal(W.words(seed, stream, n, start), W.words_numpy(seed, stream, n, start))
+    w = [W.words_numpy(4, k, 4097) for k in (1, 2, 3)]
+    acc = w[0] & w[1] & w[2]
+    assert np.array_equal(W.and_of_q(4, 3, 4097, 64), acc)
+    assert np.array_equal(W.and_of_q(4, 3, 4097, 32), (acc >> np.uint64(32)).astype(np.uint32))
+    assert np.array_equal(W.uniform(4, 4097, 32), (w[0] >> np.uint64(32)).astype(np.uint32))

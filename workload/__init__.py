@@ -22,7 +22,10 @@ log-normal segment lengths of the batched segmented workload.
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 
 import numpy as np
 
@@ -56,8 +59,36 @@ def base(seed: int, stream: int) -> np.uint64:
     return np.uint64(mix64_int(((seed << 8) | stream) & ((1 << 64) - 1)))
 
 
-def words(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
-    """word(seed, stream, i) for i in [start, start + n) as uint64."""
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_GEN_SRC = os.path.join(_HERE, "gen.c")
+_GEN_LIB = os.path.join(_HERE, "libgen.so")
+_gen = None
+
+
+def build(force: bool = True) -> str:
+    """Compile gen.c (the fast form of the same generator) with gcc."""
+    if force or not os.path.exists(_GEN_LIB) or \
+            os.path.getmtime(_GEN_LIB) < os.path.getmtime(_GEN_SRC):
+        tmp = _GEN_LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _GEN_SRC, "-o", tmp])
+        os.replace(tmp, _GEN_LIB)
+    return _GEN_LIB
+
+
+def _fast():
+    global _gen
+    if _gen is None:
+        L = ctypes.CDLL(build(force=False))
+        for f in ("gen_words", "gen_and_words", "gen_words_hi32", "gen_and_words_hi32"):
+            getattr(L, f).argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_size_t,
+                                      ctypes.c_void_p]
+            getattr(L, f).restype = None
+        _gen = L
+    return _gen
+
+
+def words_numpy(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """word(seed, stream, i) for i in [start, start + n): the numpy definition."""
     out = np.empty(n, dtype=np.uint64)
     b = base(seed, stream)
     for c0 in range(0, n, _CHUNK):
@@ -65,6 +96,14 @@ def words(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
         i = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.uint64)
         with np.errstate(over="ignore"):
             out[c0:c1] = mix64(b + i * GAMMA)
+    return out
+
+
+def words(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """word(seed, stream, i) for i in [start, start + n) as uint64 (C fast path)."""
+    out = np.empty(n, dtype=np.uint64)
+    if n:
+        _fast().gen_words(int(base(seed, stream)), start, n, out.ctypes.data)
     return out
 
 
@@ -78,6 +117,11 @@ def _narrow(w: np.ndarray, key_bits: int) -> np.ndarray:
 
 def uniform(seed: int, n: int, key_bits: int = 32, stream: int = 1) -> np.ndarray:
     """Uniform keys: the entropy band q = 1."""
+    if key_bits == 32:
+        out = np.empty(n, dtype=np.uint32)
+        if n:
+            _fast().gen_words_hi32(int(base(seed, stream)), 0, n, out.ctypes.data)
+        return out
     return _narrow(words(seed, stream, n), key_bits)
 
 
@@ -89,14 +133,11 @@ def and_of_q(seed: int, q: int, n: int, key_bits: int = 32) -> np.ndarray:
     """
     if q < 1:
         raise ValueError("q >= 1")
-    dt = np.uint32 if key_bits == 32 else np.uint64
-    out = np.empty(n, dtype=dt)
-    for c0 in range(0, n, _CHUNK):
-        c1 = min(n, c0 + _CHUNK)
-        acc = words(seed, 1, c1 - c0, start=c0)
+    out = uniform(seed, n, key_bits, stream=1)
+    if n:
+        f = _fast().gen_and_words_hi32 if key_bits == 32 else _fast().gen_and_words
         for k in range(2, q + 1):
-            acc &= words(seed, k, c1 - c0, start=c0)
-        out[c0:c1] = _narrow(acc, key_bits)
+            f(int(base(seed, k)), 0, n, out.ctypes.data)
     return out
 
 
