@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--hist-blocks-per-cu", type=int, default=0)
+    ap.add_argument("--rank", type=int, default=0, help="0 default, 1 ballot, 2 presence")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -151,8 +152,10 @@ def main():
         tr.capacity = launches_per_step
         traces.append(tr)
         holders.append((evs, arr))
-    cfg_plain = ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu)
-    cfgs = [ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu, trace=tr) for tr in traces]
+    cfg_plain = ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu,
+                               rank_algorithm=args.rank)
+    cfgs = [ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu,
+                           rank_algorithm=args.rank, trace=tr) for tr in traces]
     temp = torch.empty(ow.sort_temp_bytes(n, key_bits, has_vals, config=cfg_plain),
                        dtype=torch.uint8, device="cuda")
 

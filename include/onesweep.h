@@ -97,6 +97,8 @@ typedef struct {
     int block_threads;       /* binning workgroup size: 256, 512 or 1024 */
     int items_per_thread;    /* binning items per thread */
     int hist_blocks_per_cu;  /* histogram grid = CUs x this (persistent, tile-cyclic) */
+    int rank_algorithm;      /* wave-level digit match: 0 default, 1 one ballot per
+                                digit bit, 2 LDS presence masks (same output) */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 

@@ -82,6 +82,10 @@ onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t
       return fail(ONESWEEP_ERROR_INVALID_VALUE, "hist_blocks_per_cu %d out of [0, 64]",
                   cfg->hist_blocks_per_cu);
     if (cfg->hist_blocks_per_cu != 0) r->hist_blocks_per_cu = cfg->hist_blocks_per_cu;
+    if (cfg->rank_algorithm < 0 || cfg->rank_algorithm > 2)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "rank_algorithm %d not in [0, 2]",
+                  cfg->rank_algorithm);
+    if (cfg->rank_algorithm != 0) r->shape.rank = cfg->rank_algorithm - 1;
     r->trace = cfg->trace;
     if (r->trace && (r->trace->capacity < 0 || r->trace->capacity > ONESWEEP_TRACE_MAX ||
                      (r->trace->capacity > 0 && r->trace->events == nullptr)))
@@ -89,8 +93,8 @@ onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t
   }
   if (!binning_shape_supported(r->shape))
     return fail(ONESWEEP_ERROR_UNSUPPORTED,
-                "binning shape (key_bits=%d, values=%d, block=%d, items=%d) not built", key_bits,
-                (int)has_values, r->shape.block, r->shape.ipt);
+                "binning shape (key_bits=%d, values=%d, block=%d, items=%d, rank=%d) not built",
+                key_bits, (int)has_values, r->shape.block, r->shape.ipt, r->shape.rank + 1);
   return ONESWEEP_SUCCESS;
 }
 

@@ -26,8 +26,42 @@
 
 namespace onesweep {
 
-template <typename K, bool kVals, int kBlock, int kIpt>
-__global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
+// Two ways to find, for every lane of a wavefront, the lanes holding the
+// same digit (its "peers"), which is all the multi-split needs:
+//  - kRankBallot: one ballot per digit bit; a lane ANDs each ballot or its
+//    complement, by the value of its own bit (the paper's description);
+//  - kRankPresence: every lane ORs its lane bit into a 64-bit presence mask
+//    per digit in LDS and reads the mask back. OR is order-independent, so
+//    the mask is exact whatever order the LDS serves the lanes in, and it
+//    costs a few instructions per batch instead of four per digit bit.
+enum RankAlgorithm : int { kRankBallot = 0, kRankPresence = 1 };
+
+// Drop any global store whose index is not below n. Consistent counts never
+// produce such an index; the check only turns a logic error into a wrong
+// result instead of a memory fault.
+#ifndef ONESWEEP_CHECKED_STORES
+#define ONESWEEP_CHECKED_STORES 1
+#endif
+constexpr bool kCheckedStores = ONESWEEP_CHECKED_STORES != 0;
+
+#ifndef ONESWEEP_LOOKBACK_WINDOW
+#define ONESWEEP_LOOKBACK_WINDOW 4
+#endif
+
+// Predecessor tiles read per look-back round trip.
+constexpr int kLookback = ONESWEEP_LOOKBACK_WINDOW;
+
+// Occupancy target (waves per SIMD the register allocation must allow):
+// as high as the key registers permit without spilling.
+template <typename K, int kIpt>
+constexpr int binning_waves_per_eu() {
+  return (kIpt * sizeof(K)) <= 32 ? 8 : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
+}
+
+template <typename K, bool kVals, int kBlock, int kIpt, int kRank>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(binning_waves_per_eu<K, kIpt>())))
+    binning_kernel(BinningArgs<K> a) {
   constexpr int kWaves = kBlock / kWave;
   constexpr int kTile = kBlock * kIpt;
   constexpr int kWaveItems = kWave * kIpt;
@@ -43,17 +77,19 @@ __global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
   const K *__restrict__ src = a.keys[src_id];
   K *__restrict__ dst = a.keys[dst_id];
 
+  // Per-wave rank state, one entry per digit: the running count of the digit
+  // in the wave (word 0) and, for kRankPresence, the 64-bit presence mask
+  // (words 2-3). The region is reused for the regrouped tile afterwards.
+  constexpr int kEntryWords = kRank == kRankPresence ? 4 : 1;
   constexpr size_t kKeyBytes = sizeof(K) * kTile;
-  constexpr size_t kCountBytes = sizeof(uint32_t) * kWaves * kRadix;
-  constexpr size_t kStageBytes = kKeyBytes > kCountBytes ? kKeyBytes : kCountBytes;
-  // One LDS region serves first as the per-wave digit counters, then as the
-  // tile regrouped by digit (keys, then values).
+  constexpr size_t kRankBytes = sizeof(uint32_t) * kWaves * kRadix * kEntryWords;
+  constexpr size_t kStageBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
   __shared__ __attribute__((aligned(16))) unsigned char s_stage[kStageBytes];
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_wave_sum[kRadix / kWave];
   __shared__ uint32_t s_tile;
 
-  uint32_t(*counts)[kRadix] = reinterpret_cast<uint32_t(*)[kRadix]>(s_stage);
+  uint32_t *s_rank = reinterpret_cast<uint32_t *>(s_stage);
   K *s_keys = reinterpret_cast<K *>(s_stage);
   uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_stage);
 
@@ -61,10 +97,15 @@ __global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
   const int shift = a.shift;
-  const uint32_t mask = (1u << a.width) - 1u;
+  const int width = a.width;
+  const uint32_t mask = (1u << width) - 1u;
   const uint32_t n = a.n;
 
-  for (int i = tid; i < kWaves * kRadix; i += kBlock) (&counts[0][0])[i] = 0u;
+  {
+    uint4 *z = reinterpret_cast<uint4 *>(s_rank);
+    for (int i = tid; i < static_cast<int>(kRankBytes / 16); i += kBlock)
+      z[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
   if (tid == 0) s_tile = atomicAdd(a.tile_counter, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
@@ -88,23 +129,46 @@ __global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
     }
   }
 
-  // 2. Wave64 multi-split ranking.
+  // 2. Wave64 multi-split ranking: pos[i] becomes the key's rank among the
+  // wave's earlier keys with the same digit.
   uint32_t pos[kIpt];
+  const uint32_t wave_table = static_cast<uint32_t>(wave) * kRadix * kEntryWords;
 #pragma unroll
   for (int i = 0; i < kIpt; ++i) {
     const uint32_t d = digit_of(key[i], shift, mask);
-    uint64_t peers = ~0ull;
+    const uint32_t e = wave_table + d * kEntryWords;
+    uint32_t peers_lo, peers_hi;
+    if constexpr (kRank == kRankPresence) {
+      uint64_t *presence = reinterpret_cast<uint64_t *>(s_rank + e + 2);
+      __hip_atomic_fetch_or(presence, 1ull << lane, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_WORKGROUP);
+      __builtin_amdgcn_wave_barrier();
+      peers_lo = s_rank[e + 2];
+      peers_hi = s_rank[e + 3];
+    } else {
+      peers_lo = ~0u;
+      peers_hi = ~0u;
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-      const uint32_t bit = (d >> b) & 1u;
-      const uint64_t vote = __ballot(bit);
-      const uint64_t mine = bit ? ~0ull : 0ull;
-      peers &= ~(vote ^ mine);
+      for (int b = 0; b < kRadixBits; ++b) {
+        // Bits at or above the place width are 0 in every lane: the vote is
+        // empty and the mask is unchanged.
+        const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);  // 0 or -1
+        const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
+        peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
+        peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
+      }
     }
-    const uint32_t below = count_below(peers);
-    const uint32_t prior = counts[wave][d];
-    pos[i] = prior + below;
-    if (below == 0u) counts[wave][d] = prior + static_cast<uint32_t>(__popcll(peers));
+    const uint32_t prior = s_rank[e];
+    pos[i] = prior + __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+    // Every lane of the group stores the same new count (and clears the
+    // presence mask), so the result does not depend on which store lands.
+    const uint32_t next = prior + static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi));
+    if constexpr (kRank == kRankPresence) {
+      *reinterpret_cast<uint4 *>(s_rank + e) = make_uint4(next, 0u, 0u, 0u);
+    } else {
+      s_rank[e] = next;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
 
@@ -114,9 +178,10 @@ __global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
   if (tid < kRadix) {
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = counts[w][tid];
-      counts[w][tid] = total;
-      total += c;
+      uint32_t &c = s_rank[(w * kRadix + tid) * kEntryWords];
+      const uint32_t v = c;
+      c = total;
+      total += v;
     }
     published = total;
     if (!full && static_cast<uint32_t>(tid) == mask) published -= kTile - tile_count;
@@ -136,12 +201,13 @@ __global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
   if (tid < kRadix) {
     for (int w = 0; w < wave; ++w) local_start += s_wave_sum[w];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) counts[w][tid] += local_start;
+    for (int w = 0; w < kWaves; ++w) s_rank[(w * kRadix + tid) * kEntryWords] += local_start;
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < kIpt; ++i) pos[i] += counts[wave][digit_of(key[i], shift, mask)];
-  __syncthreads();  // the counters are dead; the region now holds the tile
+  for (int i = 0; i < kIpt; ++i)
+    pos[i] += s_rank[wave_table + digit_of(key[i], shift, mask) * kEntryWords];
+  __syncthreads();  // the rank tables are dead; the region now holds the tile
 
   // 5a. Regroup the keys by digit in LDS.
 #pragma unroll
@@ -158,22 +224,39 @@ __global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
   }
 
   // 4b. Decoupled look-back: thread v sums the counts of earlier tiles for
-  // digit v, walking backwards until it meets an inclusive prefix.
+  // digit v, walking backwards until it meets an inclusive prefix. Each round
+  // trip reads a window of kLookback predecessors at once; tiles before the
+  // first one read as an inclusive prefix of zero.
   if (tid < kRadix) {
     const uint32_t bin_start = a.bin_offsets[tid];
     uint32_t exclusive = 0u;
     if (tile != 0u) {
-      uint32_t pred = tile - 1u;
+      int pred = static_cast<int>(tile) - 1;
       while (true) {
-        const uint32_t s = load_status(&a.status[static_cast<size_t>(pred) * kRadix + tid]);
-        const uint32_t flag = s & kFlagMask;
-        if (flag == 0u) {
-          __builtin_amdgcn_s_sleep(1);
-          continue;
+        uint32_t s[kLookback];
+#pragma unroll
+        for (int w = 0; w < kLookback; ++w)
+          s[w] = pred - w >= 0
+                     ? load_status(&a.status[static_cast<size_t>(pred - w) * kRadix + tid])
+                     : kFlagG;
+        bool found = false, stalled = false;
+        int consumed = 0;
+#pragma unroll
+        for (int w = 0; w < kLookback; ++w) {
+          if (!found && !stalled) {
+            const uint32_t flag = s[w] & kFlagMask;
+            if (flag == 0u) {
+              stalled = true;
+            } else {
+              exclusive += s[w] & kValueMask;
+              ++consumed;
+              found = flag == kFlagG;
+            }
+          }
         }
-        exclusive += s & kValueMask;
-        if (flag == kFlagG) break;
-        --pred;
+        if (found) break;
+        pred -= consumed;
+        if (stalled) __builtin_amdgcn_s_sleep(1);
       }
       store_status(&a.status[static_cast<size_t>(tile) * kRadix + tid],
                    kFlagG | (exclusive + published));
@@ -192,7 +275,7 @@ __global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
     if (full || q < tile_count) {
       const K k = s_keys[q];
       const uint32_t g = s_gbase[digit_of(k, shift, mask)] + q;
-      if (g < n) dst[g] = k;  // always true when the counts are consistent
+      if (!kCheckedStores || g < n) dst[g] = k;
       if constexpr (kVals) dst_idx[i] = g;
     }
   }
@@ -207,49 +290,69 @@ __global__ void __launch_bounds__(kBlock) binning_kernel(BinningArgs<K> a) {
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t q = i * kBlock + tid;
-      if ((full || q < tile_count) && dst_idx[i] < n) vdst[dst_idx[i]] = s_vals[q];
+      if ((full || q < tile_count) && (!kCheckedStores || dst_idx[i] < n))
+        vdst[dst_idx[i]] = s_vals[q];
     }
   }
 }
 
-// Instantiated shapes: (key type, values, workgroup size, items per thread).
-#define ONESWEEP_BINNING_SHAPES(X) \
-  X(uint32_t, false, 256, 16)      \
-  X(uint32_t, false, 512, 16)      \
-  X(uint32_t, false, 512, 12)      \
-  X(uint32_t, false, 256, 24)      \
-  X(uint32_t, false, 1024, 8)      \
-  X(uint32_t, true, 256, 16)       \
-  X(uint32_t, true, 512, 16)       \
-  X(uint32_t, true, 512, 12)       \
-  X(uint32_t, true, 256, 24)       \
-  X(uint64_t, false, 256, 16)      \
-  X(uint64_t, false, 512, 8)       \
-  X(uint64_t, false, 512, 12)      \
-  X(uint64_t, true, 256, 16)       \
-  X(uint64_t, true, 512, 8)        \
-  X(uint64_t, true, 512, 12)
+// Instantiated shapes: (key type, values, workgroup size, items per thread,
+// rank algorithm).
+#define ONESWEEP_BINNING_SHAPES(X)    \
+  X(uint32_t, false, 256, 16, 0)      \
+  X(uint32_t, false, 512, 16, 0)      \
+  X(uint32_t, false, 512, 12, 0)      \
+  X(uint32_t, false, 256, 24, 0)      \
+  X(uint32_t, false, 1024, 8, 0)      \
+  X(uint32_t, false, 256, 16, 1)      \
+  X(uint32_t, false, 512, 16, 1)      \
+  X(uint32_t, false, 512, 12, 1)      \
+  X(uint32_t, false, 256, 24, 1)      \
+  X(uint32_t, false, 1024, 8, 1)      \
+  X(uint32_t, true, 256, 16, 0)       \
+  X(uint32_t, true, 512, 16, 0)       \
+  X(uint32_t, true, 512, 12, 0)       \
+  X(uint32_t, true, 256, 24, 0)       \
+  X(uint32_t, true, 256, 16, 1)       \
+  X(uint32_t, true, 512, 16, 1)       \
+  X(uint32_t, true, 512, 12, 1)       \
+  X(uint32_t, true, 256, 24, 1)       \
+  X(uint64_t, false, 256, 16, 0)      \
+  X(uint64_t, false, 512, 8, 0)       \
+  X(uint64_t, false, 512, 12, 0)      \
+  X(uint64_t, false, 256, 16, 1)      \
+  X(uint64_t, false, 512, 8, 1)       \
+  X(uint64_t, false, 512, 12, 1)      \
+  X(uint64_t, true, 256, 16, 0)       \
+  X(uint64_t, true, 512, 8, 0)        \
+  X(uint64_t, true, 512, 12, 0)       \
+  X(uint64_t, true, 256, 16, 1)       \
+  X(uint64_t, true, 512, 8, 1)        \
+  X(uint64_t, true, 512, 12, 1)
 
 bool binning_shape_supported(const BinningShape &s) {
-#define ONESWEEP_MATCH(K, V, B, I) \
-  if (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I) return true;
+#define ONESWEEP_MATCH(K, V, B, I, R)                                                  \
+  if (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I && \
+      s.rank == R)                                                                          \
+    return true;
   ONESWEEP_BINNING_SHAPES(ONESWEEP_MATCH)
 #undef ONESWEEP_MATCH
   return false;
 }
 
 BinningShape binning_default_shape(int key_bits, bool has_values) {
-  if (key_bits == 64) return BinningShape{64, has_values, 512, 8};
-  return BinningShape{32, has_values, 512, 16};
+  if (key_bits == 64) return BinningShape{64, has_values, 512, 8, kRankPresence};
+  return BinningShape{32, has_values, 512, 16, kRankPresence};
 }
 
 hipError_t launch_binning(const BinningShape &s, const void *args, uint32_t grid,
                           hipStream_t stream) {
-#define ONESWEEP_LAUNCH(K, V, B, I)                                                          \
-  if (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I) { \
-    hipLaunchKernelGGL((binning_kernel<K, V, B, I>), dim3(grid), dim3(B), 0, stream,          \
-                       *static_cast<const BinningArgs<K> *>(args));                          \
-    return hipGetLastError();                                                                \
+#define ONESWEEP_LAUNCH(K, V, B, I, R)                                                       \
+  if (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I &&  \
+      s.rank == R) {                                                                          \
+    hipLaunchKernelGGL((binning_kernel<K, V, B, I, R>), dim3(grid), dim3(B), 0, stream,        \
+                       *static_cast<const BinningArgs<K> *>(args));                           \
+    return hipGetLastError();                                                                 \
   }
   ONESWEEP_BINNING_SHAPES(ONESWEEP_LAUNCH)
 #undef ONESWEEP_LAUNCH

@@ -11,13 +11,15 @@
 
 namespace onesweep {
 
-// One binning-kernel instantiation: key width, values or not, workgroup size
-// and items per thread (tile = block * ipt keys).
+// One binning-kernel instantiation: key width, values or not, workgroup size,
+// items per thread (tile = block * ipt keys) and the wave-level match used
+// for ranking (0: one ballot per digit bit, 1: LDS presence masks).
 struct BinningShape {
   int key_bits;
   bool has_values;
   int block;
   int ipt;
+  int rank;
 };
 
 bool binning_shape_supported(const BinningShape &s);

@@ -62,16 +62,18 @@ def test_histogram_empty_and_unaligned(ow):
 
 SHAPES = {
     (32, False): [(256, 16), (512, 16), (512, 12), (256, 24), (1024, 8)],
-    (32, True): [(256, 16), (512, 16), (512, 12), (256, 24)],
-    (64, False): [(256, 16), (512, 8), (512, 12)],
-    (64, True): [(256, 16), (512, 8), (512, 12)],
+    (32, True): [(256, 16), (512, 16), (512, 12), (256, 24), (1024, 8)],
+    (64, False): [(256, 16), (512, 8), (512, 12), (1024, 8)],
+    (64, True): [(256, 16), (512, 8), (512, 12), (1024, 8)],
 }
+RANKS = (1, 2)  # one ballot per digit bit; LDS presence masks
 
 
 @pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
-def test_binning_pass_parity_and_final_status(ow, kb, vals):
+@pytest.mark.parametrize("rank", RANKS)
+def test_binning_pass_parity_and_final_status(ow, kb, vals, rank):
     for block, ipt in SHAPES[(kb, vals)]:
-        cfg = ow.make_config(block_threads=block, items_per_thread=ipt)
+        cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank)
         T = ow.tile_items(kb, vals, cfg)
         assert T == block * ipt
         for n in (1, T - 1, T, T + 1, 5 * T + 77):
@@ -120,9 +122,10 @@ def check_sort(ow, keys, vals, begin, end, cfg=None, inplace=False):
 
 
 @pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
-def test_sort_every_shape_ragged_sizes(ow, kb, vals):
+@pytest.mark.parametrize("rank", RANKS)
+def test_sort_every_shape_ragged_sizes(ow, kb, vals, rank):
     for block, ipt in SHAPES[(kb, vals)]:
-        cfg = ow.make_config(block_threads=block, items_per_thread=ipt)
+        cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank)
         T = block * ipt
         for n in (2, T - 1, T + 1, 7 * T + 333):
             keys = W.uniform(7 + n % 13, n, kb)
@@ -136,8 +139,10 @@ def test_sort_every_shape_ragged_sizes(ow, kb, vals):
 def test_sort_distributions(ow, kb, dist):
     n = 300001
     keys = keys_of(dist, 17, n, kb)
-    check_sort(ow, keys, None, 0, kb)
-    check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb)
+    for rank in RANKS:
+        cfg = ow.make_config(rank_algorithm=rank)
+        check_sort(ow, keys, None, 0, kb, cfg)
+        check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb, cfg)
 
 
 @pytest.mark.parametrize("kb", [32, 64])
