@@ -99,9 +99,6 @@ typedef struct {
     int hist_blocks_per_cu;  /* histogram grid = CUs x this (persistent, tile-cyclic) */
     int rank_algorithm;      /* wave-level digit match: 0 default, 1 one ballot per
                                 digit bit, 2 LDS presence masks (same output) */
-    int scan_agents;         /* chained-scan propagation: 0 default, -1 every tile
-                                walks back itself (decoupled look-back), 1, 2 or 4
-                                dedicated agent workgroups (same output) */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 

@@ -44,8 +44,7 @@ class Trace(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_int), ("block_threads", ctypes.c_int),
                 ("items_per_thread", ctypes.c_int), ("hist_blocks_per_cu", ctypes.c_int),
-                ("rank_algorithm", ctypes.c_int), ("scan_agents", ctypes.c_int),
-                ("trace", ctypes.POINTER(Trace))]
+                ("rank_algorithm", ctypes.c_int), ("trace", ctypes.POINTER(Trace))]
 
 
 _vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
@@ -91,15 +90,10 @@ RANK_DEFAULT, RANK_BALLOT, RANK_PRESENCE = 0, 1, 2
 
 
 def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,
-                digit_bits: int = 0, rank_algorithm: int = 0, scan_agents: int = 0,
+                digit_bits: int = 0, rank_algorithm: int = 0,
                 trace: Trace | None = None) -> Config:
-    """Kernel configuration; 0 everywhere selects the defaults.
-
-    scan_agents: -1 = every tile walks back itself (the paper's decoupled
-    look-back), 1/2/4 = that many dedicated scan-agent workgroups.
-    """
     c = Config(digit_bits, block_threads, items_per_thread, hist_blocks_per_cu, rank_algorithm,
-               scan_agents, None)
+               None)
     if trace is not None:
         c.trace = ctypes.pointer(trace)
     return c

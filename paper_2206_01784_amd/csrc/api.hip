@@ -64,7 +64,6 @@ onesweep_status_t device_cus(int *cus) {
 // Resolved kernel configuration.
 struct Resolved {
   BinningShape shape;
-  int agents;
   int hist_blocks_per_cu;
   onesweep_trace_t *trace;
 };
@@ -72,7 +71,6 @@ struct Resolved {
 onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t *cfg,
                           Resolved *r) {
   r->shape = binning_default_shape(key_bits, has_values);
-  r->agents = kDefaultScanAgents;
   r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
   r->trace = nullptr;
   if (cfg != nullptr) {
@@ -88,12 +86,6 @@ onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t
       return fail(ONESWEEP_ERROR_INVALID_VALUE, "rank_algorithm %d not in [0, 2]",
                   cfg->rank_algorithm);
     if (cfg->rank_algorithm != 0) r->shape.rank = cfg->rank_algorithm - 1;
-    if (cfg->scan_agents != 0 && cfg->scan_agents != -1 && cfg->scan_agents != 1 &&
-        cfg->scan_agents != 2 && cfg->scan_agents != 4)
-      return fail(ONESWEEP_ERROR_INVALID_VALUE, "scan_agents %d not in {-1, 0, 1, 2, 4}",
-                  cfg->scan_agents);
-    if (cfg->scan_agents == -1) r->agents = 0;
-    if (cfg->scan_agents > 0) r->agents = cfg->scan_agents;
     r->trace = cfg->trace;
     if (r->trace && (r->trace->capacity < 0 || r->trace->capacity > ONESWEEP_TRACE_MAX ||
                      (r->trace->capacity > 0 && r->trace->events == nullptr)))
@@ -292,9 +284,8 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
       a.place = j;
       a.shift = lo;
       a.width = width;
-      a.agents = static_cast<uint32_t>(rc.agents);
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                      launch_binning(rc.shape, &a, L.tiles + rc.agents, stream));
+                      launch_binning(rc.shape, &a, L.tiles, stream));
     } else {
       BinningArgs<uint64_t> a{};
       for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<uint64_t *>(ca.keys[b]);
@@ -307,9 +298,8 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
       a.place = j;
       a.shift = lo;
       a.width = width;
-      a.agents = static_cast<uint32_t>(rc.agents);
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                      launch_binning(rc.shape, &a, L.tiles + rc.agents, stream));
+                      launch_binning(rc.shape, &a, L.tiles, stream));
     }
   }
   ca.plan = plan;
@@ -441,9 +431,8 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.place = 0;
     a.shift = shift;
     a.width = width;
-    a.agents = static_cast<uint32_t>(rc.agents);
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                    launch_binning(rc.shape, &a, tiles + rc.agents, s));
+                    launch_binning(rc.shape, &a, tiles, s));
   } else {
     BinningArgs<uint64_t> a{};
     a.keys[kBufIn] = static_cast<uint64_t *>(const_cast<void *>(d_src_keys));
@@ -458,9 +447,8 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.place = 0;
     a.shift = shift;
     a.width = width;
-    a.agents = static_cast<uint32_t>(rc.agents);
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                    launch_binning(rc.shape, &a, tiles + rc.agents, s));
+                    launch_binning(rc.shape, &a, tiles, s));
   }
   return ONESWEEP_SUCCESS;
 }

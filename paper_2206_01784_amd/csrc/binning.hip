@@ -55,93 +55,7 @@ constexpr int kLookback = ONESWEEP_LOOKBACK_WINDOW;
 // as high as the key registers permit without spilling.
 template <typename K, int kIpt>
 constexpr int binning_waves_per_eu() {
-  return (kIpt * sizeof(K)) <= 32 ? 8 : ((kIpt * sizeof(K)) <= 48 ? 5 : 4);
-}
-
-// Scan agent (used when BinningArgs::agents > 0). The paper's decoupled
-// look-back lets every tile walk back over its predecessors' counts until it
-// meets an inclusive prefix; the time a tile needs to find one grows with
-// the rate at which tiles are issued, because every tile publishes its own
-// prefix only after its own walk. Across the eight XCDs of MI355X the status
-// words travel through the device-coherent path, which makes that walk the
-// dominant cost of a pass. An agent instead computes the same chained scan
-// in tile order: it reads the status rows of the next slots * kAgentRows
-// tiles at once, extends the running prefix over the leading run of tiles
-// that have published their counts, and writes each of those tiles'
-// inclusive prefix (status G). Tiles then only wait for the word of their
-// immediate predecessor. Agents take the first tickets, so they are running
-// before any tile; every tile publishes its count without waiting, so the
-// agent always progresses. The status words, values and final state are
-// those of the paper's scheme (Figures 6 and 7f).
-constexpr int kAgentRows = 16;
-
-template <int kBlock>
-__device__ void scan_agent(uint32_t *status, uint32_t tiles, uint32_t agent, uint32_t agents,
-                           uint32_t *lds) {
-  const int digits = kRadix / static_cast<int>(agents);  // 256, 128 or 64
-  const int waves_per_slot = digits / kWave;
-  const int slots = (kBlock / kWave) / waves_per_slot;
-  const int wave = threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  const int slot = wave / waves_per_slot;
-  const int local = (wave % waves_per_slot) * kWave + lane;
-  const int digit = static_cast<int>(agent) * digits + local;
-  uint32_t *s_valid = lds;                   // [slots][digits]
-  uint32_t *s_sum = lds + slots * digits;    // [slots][digits]
-  uint32_t cursor = 0u, prefix = 0u;
-  while (true) {
-    const uint32_t first = cursor + static_cast<uint32_t>(slot * kAgentRows);
-    uint32_t st[kAgentRows];
-#pragma unroll
-    for (int k = 0; k < kAgentRows; ++k)
-      st[k] = first + k < tiles ? load_status(&status[static_cast<size_t>(first + k) * kRadix + digit])
-                                : 0u;
-    uint32_t valid = 0u, sum = 0u;
-    bool open = true;
-#pragma unroll
-    for (int k = 0; k < kAgentRows; ++k) {
-      if (open && (st[k] & kFlagMask) != 0u) {
-        sum += st[k] & kValueMask;
-        ++valid;
-      } else {
-        open = false;
-      }
-    }
-    s_valid[slot * digits + local] = valid;
-    s_sum[slot * digits + local] = sum;
-    __syncthreads();
-    // Combine the slots in tile order up to the first slot that stopped
-    // early; later slots wait for the next round.
-    uint32_t running = prefix, advance = 0u, start = 0u;
-    bool blocked = false, mine = false;
-    for (int g = 0; g < slots; ++g) {
-      if (g == slot) {
-        mine = !blocked;
-        start = running;
-      }
-      if (!blocked) {
-        const uint32_t v = s_valid[g * digits + local];
-        running += s_sum[g * digits + local];
-        advance += v;
-        blocked = v < static_cast<uint32_t>(kAgentRows);
-      }
-    }
-    if (mine) {
-      uint32_t p = start;
-#pragma unroll
-      for (int k = 0; k < kAgentRows; ++k) {
-        if (static_cast<uint32_t>(k) < valid) {
-          p += st[k] & kValueMask;
-          store_status(&status[static_cast<size_t>(first + k) * kRadix + digit], kFlagG | p);
-        }
-      }
-    }
-    prefix = running;
-    cursor += advance;
-    if (!__syncthreads_or(cursor < tiles)) break;  // also guards the LDS reuse
-    if (__builtin_amdgcn_ballot_w64(advance == 0u && cursor < tiles) != 0ull)
-      __builtin_amdgcn_s_sleep(2);
-  }
+  return (kIpt * sizeof(K)) <= 32 ? 8 : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
 }
 
 template <typename K, bool kVals, int kBlock, int kIpt, int kRank>
@@ -175,7 +89,6 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ uint32_t s_wave_sum[kRadix / kWave];
   __shared__ uint32_t s_tile;
 
-
   uint32_t *s_rank = reinterpret_cast<uint32_t *>(s_stage);
   K *s_keys = reinterpret_cast<K *>(s_stage);
   uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_stage);
@@ -195,13 +108,7 @@ __global__ void __launch_bounds__(kBlock)
   }
   if (tid == 0) s_tile = atomicAdd(a.tile_counter, 1u);
   __syncthreads();
-  const uint32_t tiles = (n + kTile - 1) / kTile;
-  if (s_tile < a.agents) {  // the first tickets run the scan agents
-    scan_agent<kBlock>(a.status, tiles, s_tile, a.agents, s_rank);
-    return;
-  }
-  const uint32_t tile = s_tile - a.agents;
-  const bool agent_scan = a.agents != 0u;
+  const uint32_t tile = s_tile;
   const uint32_t tile_base = tile * static_cast<uint32_t>(kTile);
   const uint32_t tile_count = min(n - tile_base, static_cast<uint32_t>(kTile));
   const bool full = tile_count == static_cast<uint32_t>(kTile);
@@ -239,25 +146,17 @@ __global__ void __launch_bounds__(kBlock)
       peers_lo = s_rank[e + 2];
       peers_hi = s_rank[e + 3];
     } else {
-      // miss accumulates, per lane, the lanes whose digit differs in some
-      // bit: miss |= vote ^ own in one 3-input bit operation per half
-      // (truth table 0xf6 = S0 | (S1 ^ S2)); peers = ~miss. Bits at or above
-      // the place width are 0 in every lane and change nothing.
-      uint32_t miss_lo = 0u, miss_hi = 0u;
+      peers_lo = ~0u;
+      peers_hi = ~0u;
 #pragma unroll
       for (int b = 0; b < kRadixBits; ++b) {
+        // Bits at or above the place width are 0 in every lane: the vote is
+        // empty and the mask is unchanged.
         const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);  // 0 or -1
-        uint64_t vote;
-        asm volatile("v_cmp_ne_u32_e64 %0, 0, %1" : "=s"(vote) : "v"(own));
-        asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xf6"
-            : "=v"(miss_lo)
-            : "v"(miss_lo), "s"(static_cast<uint32_t>(vote)), "v"(own));
-        asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xf6"
-            : "=v"(miss_hi)
-            : "v"(miss_hi), "s"(static_cast<uint32_t>(vote >> 32)), "v"(own));
+        const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
+        peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
+        peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
       }
-      peers_lo = ~miss_lo;
-      peers_hi = ~miss_hi;
     }
     const uint32_t prior = s_rank[e];
     pos[i] = prior + __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
@@ -275,73 +174,34 @@ __global__ void __launch_bounds__(kBlock)
 
   // 3. Per-digit sums: over waves (each wave's start inside its digit run)
   // and over digits (the run's start inside the tile).
-  // With up to 8 waves the per-wave starts stay in registers; with more
-  // they are written back now and adjusted by the digit's start later.
-  constexpr bool kStartsInRegs = kWaves <= 8;
   uint32_t total = 0u, local_start = 0u, published = 0u;
-  uint32_t wave_start[kStartsInRegs ? kWaves : 1];
-  // Thread v < 256 looks back for digit v. Its first window of kLookback
-  // predecessors is issued now, so the latency overlaps the local scan and
-  // the regrouping.
-  uint32_t window[kLookback];
   if (tid < kRadix) {
 #pragma unroll
-    for (int w = 0; w < kLookback; ++w) {
-      const int t = static_cast<int>(tile) - 1 - w;
-      window[w] = (t >= 0 && (w == 0 || !agent_scan))
-                      ? load_status(&a.status[static_cast<size_t>(t) * kRadix + tid])
-                      : kFlagG;
-    }
-    if constexpr (kStartsInRegs) {
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) wave_start[w] = s_rank[(w * kRadix + tid) * kEntryWords];
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t v = wave_start[w];
-        wave_start[w] = total;
-        total += v;
-      }
-    } else {
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        uint32_t &c = s_rank[(w * kRadix + tid) * kEntryWords];
-        const uint32_t v = c;
-        c = total;
-        total += v;
-      }
+    for (int w = 0; w < kWaves; ++w) {
+      uint32_t &c = s_rank[(w * kRadix + tid) * kEntryWords];
+      const uint32_t v = c;
+      c = total;
+      total += v;
     }
     published = total;
     if (!full && static_cast<uint32_t>(tid) == mask) published -= kTile - tile_count;
     // 4a. Publish this tile's count (tile 0's count is already its prefix).
-    // On gfx9 one counter tracks both loads and stores of a wave, so a wave
-    // that waits for a load also waits until its earlier stores have been
-    // written through; under a full pass of scatter traffic that takes
-    // microseconds. The look-back waves therefore hand the count to the next
-    // four waves, which store it and never wait on a global load afterwards.
-    const uint32_t word = (tile == 0u && !agent_scan ? kFlagG : kFlagL) | published;
-    if constexpr (kBlock >= 2 * kRadix)
-      s_gbase[tid] = word;
-    else
-      store_status(&a.status[static_cast<size_t>(tile) * kRadix + tid], word);
-    const uint32_t incl = wave_inclusive_sum(total);
+    store_status(&a.status[static_cast<size_t>(tile) * kRadix + tid],
+                 (tile == 0u ? kFlagG : kFlagL) | published);
+    uint32_t incl = total;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl += t;
+    }
     if (lane == kWave - 1) s_wave_sum[wave] = incl;
     local_start = incl - total;
   }
   __syncthreads();
-  if constexpr (kBlock >= 2 * kRadix) {
-    if (tid >= kRadix && tid < 2 * kRadix)
-      store_status(&a.status[static_cast<size_t>(tile) * kRadix + (tid - kRadix)],
-                   s_gbase[tid - kRadix]);
-  }
   if (tid < kRadix) {
     for (int w = 0; w < wave; ++w) local_start += s_wave_sum[w];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      if constexpr (kStartsInRegs)
-        s_rank[(w * kRadix + tid) * kEntryWords] = wave_start[w] + local_start;
-      else
-        s_rank[(w * kRadix + tid) * kEntryWords] += local_start;
-    }
+    for (int w = 0; w < kWaves; ++w) s_rank[(w * kRadix + tid) * kEntryWords] += local_start;
   }
   __syncthreads();
 #pragma unroll
@@ -364,33 +224,31 @@ __global__ void __launch_bounds__(kBlock)
   }
 
   // 4b. Decoupled look-back: thread v sums the counts of earlier tiles for
-  // digit v, walking backwards until it meets an inclusive prefix, one
-  // window of kLookback predecessors per round trip; tiles before the first
-  // one read as an inclusive prefix of zero.
+  // digit v, walking backwards until it meets an inclusive prefix. Each round
+  // trip reads a window of kLookback predecessors at once; tiles before the
+  // first one read as an inclusive prefix of zero.
   if (tid < kRadix) {
+    const uint32_t bin_start = a.bin_offsets[tid];
     uint32_t exclusive = 0u;
-    if (tile != 0u && agent_scan) {
-      // The agent publishes the predecessor's inclusive prefix.
-      uint32_t st = window[0];
-      while ((st & kFlagMask) != kFlagG) {
-        __builtin_amdgcn_s_sleep(1);
-        st = load_status(&a.status[static_cast<size_t>(tile - 1u) * kRadix + tid]);
-      }
-      exclusive = st & kValueMask;
-    } else if (tile != 0u) {
+    if (tile != 0u) {
       int pred = static_cast<int>(tile) - 1;
       while (true) {
+        uint32_t s[kLookback];
+#pragma unroll
+        for (int w = 0; w < kLookback; ++w)
+          s[w] = pred - w >= 0
+                     ? load_status(&a.status[static_cast<size_t>(pred - w) * kRadix + tid])
+                     : kFlagG;
         bool found = false, stalled = false;
         int consumed = 0;
 #pragma unroll
         for (int w = 0; w < kLookback; ++w) {
           if (!found && !stalled) {
-            const uint32_t st = window[w];
-            const uint32_t flag = st & kFlagMask;
+            const uint32_t flag = s[w] & kFlagMask;
             if (flag == 0u) {
               stalled = true;
             } else {
-              exclusive += st & kValueMask;
+              exclusive += s[w] & kValueMask;
               ++consumed;
               found = flag == kFlagG;
             }
@@ -399,18 +257,13 @@ __global__ void __launch_bounds__(kBlock)
         if (found) break;
         pred -= consumed;
         if (stalled) __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-        for (int w = 0; w < kLookback; ++w)
-          window[w] = pred - w >= 0
-                          ? load_status(&a.status[static_cast<size_t>(pred - w) * kRadix + tid])
-                          : kFlagG;
       }
       store_status(&a.status[static_cast<size_t>(tile) * kRadix + tid],
                    kFlagG | (exclusive + published));
     }
     // Global position of the key at tile position q with digit v is
     // s_gbase[v] + q (unsigned wrap-around cancels in the sum).
-    s_gbase[tid] = a.bin_offsets[tid] + exclusive - local_start;
+    s_gbase[tid] = bin_start + exclusive - local_start;
   }
   __syncthreads();
 
@@ -490,8 +343,10 @@ bool binning_shape_supported(const BinningShape &s) {
 }
 
 BinningShape binning_default_shape(int key_bits, bool has_values) {
-  if (key_bits == 64) return BinningShape{64, has_values, 512, 8, kRankPresence};
-  return BinningShape{32, has_values, 512, 16, kRankPresence};
+  // Measured on MI355X (2^28 uint32 keys / pairs, 2^27 uint64 pairs).
+  if (key_bits == 64) return BinningShape{64, has_values, 1024, 8, kRankBallot};
+  if (has_values) return BinningShape{32, true, 512, 16, kRankBallot};
+  return BinningShape{32, false, 1024, 8, kRankBallot};
 }
 
 hipError_t launch_binning(const BinningShape &s, const void *args, uint32_t grid,

@@ -47,7 +47,6 @@ struct BinningArgs {
   uint32_t *tile_counter;      // dynamic tile ids of this place
   const PassPlan *plan;        // NULL: run unconditionally in -> out
   uint32_t n;
-  uint32_t agents;             // scan-agent workgroups (0: tiles look back themselves)
   int place;
   int shift;
   int width;
@@ -75,7 +74,6 @@ __device__ __forceinline__ uint32_t load_status(const uint32_t *p) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
@@ -84,20 +82,6 @@ __device__ __forceinline__ uint32_t lane_id() {
 __device__ __forceinline__ uint32_t count_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
-}
-
-// Inclusive prefix sum across the 64 lanes of a wavefront with DPP: row
-// shifts build sums within rows of 16 lanes, then the last lane of rows 0
-// and 2 is added to rows 1 and 3 (row_bcast:15) and lane 31 to rows 2 and 3
-// (row_bcast:31). Lanes without a source lane read 0.
-__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
-  x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, false);  // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, false);  // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, false);  // row_shr:4
-  x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, false);  // row_shr:8
-  x += __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  x += __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return x;
 }
 
 template <typename K>

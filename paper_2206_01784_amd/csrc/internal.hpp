@@ -22,10 +22,6 @@ struct BinningShape {
   int rank;
 };
 
-// Scan agents used by default (0: the paper's decoupled look-back by every
-// tile, which measures faster on MI355X than the agents).
-constexpr int kDefaultScanAgents = 0;
-
 bool binning_shape_supported(const BinningShape &s);
 BinningShape binning_default_shape(int key_bits, bool has_values);
 

@@ -67,16 +67,13 @@ SHAPES = {
     (64, True): [(256, 16), (512, 8), (512, 12), (1024, 8)],
 }
 RANKS = (1, 2)  # one ballot per digit bit; LDS presence masks
-SCANS = (-1, 1, 2, 4)  # decoupled look-back by every tile; 1, 2 or 4 scan agents
 
 
 @pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
 @pytest.mark.parametrize("rank", RANKS)
-@pytest.mark.parametrize("scan", (-1, 2))
-def test_binning_pass_parity_and_final_status(ow, kb, vals, rank, scan):
+def test_binning_pass_parity_and_final_status(ow, kb, vals, rank):
     for block, ipt in SHAPES[(kb, vals)]:
-        cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank,
-                             scan_agents=scan)
+        cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank)
         T = ow.tile_items(kb, vals, cfg)
         assert T == block * ipt
         for n in (1, T - 1, T, T + 1, 5 * T + 77):
@@ -126,11 +123,9 @@ def check_sort(ow, keys, vals, begin, end, cfg=None, inplace=False):
 
 @pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
 @pytest.mark.parametrize("rank", RANKS)
-@pytest.mark.parametrize("scan", SCANS)
-def test_sort_every_shape_ragged_sizes(ow, kb, vals, rank, scan):
+def test_sort_every_shape_ragged_sizes(ow, kb, vals, rank):
     for block, ipt in SHAPES[(kb, vals)]:
-        cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank,
-                             scan_agents=scan)
+        cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank)
         T = block * ipt
         for n in (2, T - 1, T + 1, 7 * T + 333):
             keys = W.uniform(7 + n % 13, n, kb)
@@ -145,10 +140,9 @@ def test_sort_distributions(ow, kb, dist):
     n = 300001
     keys = keys_of(dist, 17, n, kb)
     for rank in RANKS:
-        for scan in (-1, 2):
-            cfg = ow.make_config(rank_algorithm=rank, scan_agents=scan)
-            check_sort(ow, keys, None, 0, kb, cfg)
-            check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb, cfg)
+        cfg = ow.make_config(rank_algorithm=rank)
+        check_sort(ow, keys, None, 0, kb, cfg)
+        check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb, cfg)
 
 
 @pytest.mark.parametrize("kb", [32, 64])
@@ -189,12 +183,6 @@ def test_one_million_uniform_u32_keys(ow, seed):
     """2^20 uniform uint32 keys, 8-bit digits, 4 passes, bit-exact."""
     keys = W.uniform(seed, 1 << 20)
     check_sort(ow, keys, None, 0, 32)
-    check_sort(ow, keys, None, 0, 32, ow.make_config(scan_agents=-1))
-
-
-def test_invalid_scan_agents_rejected(ow):
-    with pytest.raises(ow.OnesweepError):
-        ow.sort_keys(dev(W.uniform(1, 1000)), config=ow.make_config(scan_agents=3))
 
 
 def test_trace_records_the_launch_sequence(ow):
