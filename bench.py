@@ -72,6 +72,75 @@ def read_traffic(launch_bytes_alg: float):
         return None
 
 
+def _read_counters(path):
+    """{kernel name: [counter value per dispatch]} from a rocprofv3 counter CSV."""
+    import csv
+    out = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name") or row.get("Kernel-Name") or ""
+            val = row.get("Counter_Value") or row.get("Counter-Value")
+            if val is None:
+                continue
+            out.setdefault(name, []).append(float(val))
+    return out
+
+
+def summarize_counters(fetch_csv, write_csv, workload="u32_keys_uniform"):
+    """Write the binning kernel's measured HBM traffic per launch.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each binning launch are
+    scaled by bytes / counter of the plain copy kernel in the same run, whose
+    true traffic is known (n * key bytes read and written).
+    """
+    import statistics as st
+    key_bits, has_vals, dist, log2n = WORKLOADS[workload]
+    n = 1 << log2n
+    copy_bytes = n * (key_bits // 8 + (4 if has_vals else 0))
+    fetch, write = _read_counters(fetch_csv), _read_counters(write_csv)
+
+    def pick(d, sub):
+        vals = [v for k, vs in d.items() if sub in k for v in vs]
+        if not vals:
+            raise SystemExit(f"no dispatches of {sub} in the counter file")
+        return vals
+
+    copy_f = max(pick(fetch, "copy_kernel")) * 1024
+    copy_w = max(pick(write, "copy_kernel")) * 1024
+    bin_f = st.mean(pick(fetch, "binning_kernel")) * 1024
+    bin_w = st.mean(pick(write, "binning_kernel")) * 1024
+    f_scale, w_scale = copy_bytes / copy_f, copy_bytes / copy_w
+    traffic = bin_f * f_scale + bin_w * w_scale
+    alg = n * 2 * (key_bits // 8 + (4 if has_vals else 0))
+    lines = [
+        "# HBM traffic of one binning launch, from two rocprofv3 --pmc runs of bench.py",
+        f"# workload: {workload} (n = 2^{log2n})",
+        f"# fetch csv: {os.path.basename(fetch_csv)}; write csv: {os.path.basename(write_csv)}",
+        "# scale = bytes the plain copy kernel must move / its counter reading",
+        "# commands (repo root; run from /tmp with TMPDIR=/tmp):",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- "
+        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-cpu-baseline --calibrate-copy",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o write -- "
+        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-cpu-baseline --calibrate-copy",
+        "#   python bench.py --workload " + workload + " --counters-summary <fetch csv> <write csv>",
+        f"kernel_source_sha256_16: {kernel_source_hash()}",
+        f"copy_fetch_kib: {copy_f / 1024:.1f}",
+        f"copy_write_kib: {copy_w / 1024:.1f}",
+        f"copy_true_bytes_each_way: {copy_bytes}",
+        f"fetch_scale: {f_scale:.4f}",
+        f"write_scale: {w_scale:.4f}",
+        f"binning_fetch_kib_per_launch: {bin_f / 1024:.1f}",
+        f"binning_write_kib_per_launch: {bin_w / 1024:.1f}",
+        f"hbm_bytes_per_launch: {traffic:.0f}",
+        f"algorithmic_bytes_per_launch: {alg}",
+        f"traffic_over_algorithmic: {traffic / alg:.3f}",
+    ]
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def make_keys(dist, n, key_bits, seed=2):
     import workload as W
     if dist == "uniform":
@@ -112,7 +181,17 @@ def main():
     ap.add_argument("--hist-blocks-per-cu", type=int, default=0)
     ap.add_argument("--rank", type=int, default=0, help="0 default, 1 ballot, 2 presence")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run the library's plain copy kernel once on the input first "
+                         "(known size: n keys read and written), for counter scaling")
+    ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="offline: summarise two rocprofv3 --pmc runs (FETCH_SIZE, "
+                         "WRITE_SIZE) of this script into the traffic file and exit")
     args = ap.parse_args()
+
+    if args.counters_summary:
+        summarize_counters(*args.counters_summary, workload=args.workload)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -166,6 +245,15 @@ def main():
         else:
             ow.sort_keys(d_keys, out=d_kout, temp=temp, config=cfg, stream=stream)
 
+    if args.calibrate_copy:
+        # An empty bit range makes the sort a plain copy: one launch of the
+        # copy kernel reading and writing n keys (and values).
+        if has_vals:
+            ow.sort_pairs(d_keys, d_vals, 0, 0, keys_out=d_kout, values_out=d_vout,
+                          stream=stream)
+        else:
+            ow.sort_keys(d_keys, 0, 0, out=d_kout, stream=stream)
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         step(cfg_plain)
     torch.cuda.synchronize()
