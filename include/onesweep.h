@@ -65,7 +65,9 @@ typedef enum {
     ONESWEEP_KERNEL_HISTOGRAM = 1, /* phase 1: all-place histogram */
     ONESWEEP_KERNEL_SCAN = 2,      /* phase 2: exclusive sums and pass plan */
     ONESWEEP_KERNEL_BINNING = 3,   /* phase 3: one chained-scan binning pass */
-    ONESWEEP_KERNEL_COPY = 4       /* final copy when no pass (or an odd count) ran */
+    ONESWEEP_KERNEL_COPY = 4,      /* final copy when no pass (or an odd count) ran */
+    ONESWEEP_KERNEL_CLASSIFY = 5,  /* segmented sort: offsets -> classes and tiles */
+    ONESWEEP_KERNEL_LDS_SORT = 6   /* segmented sort: whole segments sorted in LDS */
 } onesweep_kernel_kind_t;
 
 #define ONESWEEP_TRACE_MAX 64
@@ -99,6 +101,11 @@ typedef struct {
     int hist_blocks_per_cu;  /* histogram grid = CUs x this (persistent, tile-cyclic) */
     int rank_algorithm;      /* wave-level digit match: 0 default, 1 one ballot per
                                 digit bit, 2 LDS presence masks (same output) */
+    int segment_limits[3];   /* segmented sort only: longest segment sorted whole in
+                                LDS by the 64-, 256- and 1024-thread class; 0 =
+                                the class's capacity (512, 2048, 8192 keys), -1 =
+                                class unused. Longer segments are binned tile by
+                                tile. */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 
@@ -153,6 +160,39 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
                                         const uint32_t *d_bin_offsets,
                                         const onesweep_config_t *cfg,
                                         onesweep_stream_t stream);
+
+/*
+ * Batched segmented sort: for every s < num_segments, the keys (and values)
+ * in [d_seg_offsets[s], d_seg_offsets[s + 1]) are sorted as in
+ * onesweep_sort_pairs, independently of every other segment; no key leaves
+ * its segment. This batching is not in the paper: each segment is sorted by
+ * the paper's method (Section 3), or, when it fits one workgroup's LDS, by
+ * the same digit passes run entirely in LDS (one read and one write of the
+ * segment).
+ *  - d_seg_offsets: num_segments + 1 uint32 in device memory, read only on the
+ *    device (the host never synchronises): non-decreasing, first 0, last n.
+ *    Empty segments are allowed. Offsets that break these rules are detected
+ *    on the device: then nothing is written to the outputs and the first
+ *    uint32 of d_temp reads 1 after the call completes (0 otherwise; it is
+ *    not written when n == 0). With begin_bit == end_bit the offsets are not
+ *    read and the output is a copy of the input.
+ *  - d_vals_in / d_vals_out: both NULL for keys only.
+ *  - In-place (in == out) is allowed for keys and for values; partial
+ *    overlap is invalid. The offsets must not overlap an output or d_temp.
+ *  - n and num_segments must be below 2^30; num_segments == 0 requires n == 0.
+ *  - cfg->segment_limits picks the segment classes; block_threads and
+ *    items_per_thread pick the binning tile of the longer segments (a
+ *    subset of the shapes of onesweep_sort_pairs is built for it).
+ * The enqueued sequence is a fixed list of kernels whatever the offsets, so
+ * it can be captured once and replayed.
+ */
+onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
+                                         const void *d_keys_in, void *d_keys_out,
+                                         const uint32_t *d_vals_in, uint32_t *d_vals_out,
+                                         size_t n, const uint32_t *d_seg_offsets,
+                                         size_t num_segments, int key_bits, int begin_bit,
+                                         int end_bit, int stable, const onesweep_config_t *cfg,
+                                         onesweep_stream_t stream);
 
 /* Binning tile size T = block_threads x items_per_thread that `cfg` resolves
  * to for this key width and value presence; 0 if the config is unsupported.

@@ -29,8 +29,10 @@ ERROR_INSUFFICIENT_TEMP = 3
 ERROR_HIP = 4
 ERROR_UNSUPPORTED = 5
 
-KERNEL_RESET, KERNEL_HISTOGRAM, KERNEL_SCAN, KERNEL_BINNING, KERNEL_COPY = range(5)
-KERNEL_NAMES = ("reset", "histogram", "scan", "binning", "copy")
+(KERNEL_RESET, KERNEL_HISTOGRAM, KERNEL_SCAN, KERNEL_BINNING, KERNEL_COPY, KERNEL_CLASSIFY,
+ KERNEL_LDS_SORT) = range(7)
+KERNEL_NAMES = ("reset", "histogram", "scan", "binning", "copy", "classify", "lds_sort")
+SEGMENT_CLASS_CAPACITY = (512, 2048, 8192)
 TRACE_MAX = 64
 RADIX_BITS = 8
 RADIX = 256
@@ -44,7 +46,8 @@ class Trace(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_int), ("block_threads", ctypes.c_int),
                 ("items_per_thread", ctypes.c_int), ("hist_blocks_per_cu", ctypes.c_int),
-                ("rank_algorithm", ctypes.c_int), ("trace", ctypes.POINTER(Trace))]
+                ("rank_algorithm", ctypes.c_int), ("segment_limits", ctypes.c_int * 3),
+                ("trace", ctypes.POINTER(Trace))]
 
 
 _vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
@@ -57,12 +60,14 @@ _lib.onesweep_sort_pairs.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _i32, _
 _lib.onesweep_histogram.argtypes = [_vp, _sz, _i32, _i32, _i32, _vp, _cfgp, _vp]
 _lib.onesweep_binning_pass.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _i32, _i32, _i32, _vp,
                                        _cfgp, _vp]
+_lib.onesweep_sort_segments.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _i32, _i32,
+                                        _i32, _i32, _cfgp, _vp]
 _lib.onesweep_tile_items.argtypes = [_i32, _i32, _cfgp]
 _lib.onesweep_tile_items.restype = _sz
 _lib.onesweep_last_error.restype = ctypes.c_char_p
 _lib.onesweep_version.restype = ctypes.c_char_p
 for _f in ("onesweep_sort_keys", "onesweep_sort_pairs", "onesweep_histogram",
-           "onesweep_binning_pass"):
+           "onesweep_binning_pass", "onesweep_sort_segments"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -90,10 +95,10 @@ RANK_DEFAULT, RANK_BALLOT, RANK_PRESENCE = 0, 1, 2
 
 
 def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,
-                digit_bits: int = 0, rank_algorithm: int = 0,
+                digit_bits: int = 0, rank_algorithm: int = 0, segment_limits=(0, 0, 0),
                 trace: Trace | None = None) -> Config:
     c = Config(digit_bits, block_threads, items_per_thread, hist_blocks_per_cu, rank_algorithm,
-               None)
+               (ctypes.c_int * 3)(*segment_limits), None)
     if trace is not None:
         c.trace = ctypes.pointer(trace)
     return c
@@ -244,3 +249,55 @@ def binning_pass(src: torch.Tensor, bin_offsets: torch.Tensor, shift: int, width
                                       n, kb, shift, width, _dev_ptr(bin_offsets),
                                       _cfg_ptr(config), _stream(stream)))
     return dst, dst_values, temp
+
+
+def sort_segments_temp_bytes(n: int, num_segments: int, key_bits: int = 32,
+                             has_values: bool = False, begin_bit: int = 0,
+                             end_bit: int | None = None, config: Config | None = None) -> int:
+    """Temporary storage of a segmented sort (pure host computation)."""
+    end_bit = key_bits if end_bit is None else end_bit
+    size = ctypes.c_size_t(0)
+    dummy = ctypes.c_void_p(4) if has_values else None
+    _check(_lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, dummy, dummy, n, None,
+                                       num_segments, key_bits, begin_bit, end_bit, 1,
+                                       _cfg_ptr(config), None))
+    return int(size.value)
+
+
+def sort_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tensor | None = None,
+                  begin_bit: int = 0, end_bit: int | None = None,
+                  keys_out: torch.Tensor | None = None, values_out: torch.Tensor | None = None,
+                  temp: torch.Tensor | None = None, config: Config | None = None, stream=None):
+    """Stable sort of every segment [offsets[s], offsets[s+1]) on its own.
+
+    offsets: uint32 device tensor of num_segments + 1 entries (0 first, n
+    last, non-decreasing). Returns keys_out, or (keys_out, values_out) when
+    values are given. After the work completes, temp[0:4] holds 1 if the
+    device found the offsets invalid (then nothing was written), else 0.
+    """
+    kb = _key_bits(keys)
+    if offsets.dtype != torch.uint32:
+        raise TypeError("offsets must be torch.uint32")
+    if offsets.numel() < 1:
+        raise ValueError("offsets needs num_segments + 1 >= 1 entries")
+    end_bit = kb if end_bit is None else end_bit
+    n = keys.numel()
+    num_segments = offsets.numel() - 1
+    has_values = values is not None
+    if has_values:
+        if values.dtype != torch.uint32:
+            raise TypeError("values must be torch.uint32")
+        if values.numel() != n:
+            raise ValueError("keys and values differ in length")
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    if has_values and values_out is None:
+        values_out = torch.empty_like(values)
+    need = sort_segments_temp_bytes(n, num_segments, kb, has_values, begin_bit, end_bit, config)
+    temp = _temp(temp, need, keys.device)
+    size = ctypes.c_size_t(temp.numel())
+    _check(_lib.onesweep_sort_segments(_dev_ptr(temp), ctypes.byref(size), _dev_ptr(keys),
+                                       _dev_ptr(keys_out), _dev_ptr(values),
+                                       _dev_ptr(values_out), n, _dev_ptr(offsets), num_segments,
+                                       kb, begin_bit, end_bit, 1, _cfg_ptr(config),
+                                       _stream(stream)))
+    return (keys_out, values_out) if has_values else keys_out

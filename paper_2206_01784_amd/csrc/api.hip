@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 
 #include "../../include/onesweep.h"
@@ -69,7 +70,7 @@ struct Resolved {
 };
 
 onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t *cfg,
-                          Resolved *r) {
+                          Resolved *r, bool segmented = false) {
   r->shape = binning_default_shape(key_bits, has_values);
   r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
   r->trace = nullptr;
@@ -91,10 +92,11 @@ onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t
                      (r->trace->capacity > 0 && r->trace->events == nullptr)))
       return fail(ONESWEEP_ERROR_INVALID_VALUE, "trace capacity/events invalid");
   }
-  if (!binning_shape_supported(r->shape))
+  if (!binning_shape_supported(r->shape, segmented))
     return fail(ONESWEEP_ERROR_UNSUPPORTED,
-                "binning shape (key_bits=%d, values=%d, block=%d, items=%d, rank=%d) not built",
-                key_bits, (int)has_values, r->shape.block, r->shape.ipt, r->shape.rank + 1);
+                "%sbinning shape (key_bits=%d, values=%d, block=%d, items=%d, rank=%d) not built",
+                segmented ? "segmented " : "", key_bits, (int)has_values, r->shape.block,
+                r->shape.ipt, r->shape.rank + 1);
   return ONESWEEP_SUCCESS;
 }
 
@@ -285,7 +287,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
       a.shift = lo;
       a.width = width;
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                      launch_binning(rc.shape, &a, L.tiles, stream));
+                      launch_binning(rc.shape, false, &a, L.tiles, stream));
     } else {
       BinningArgs<uint64_t> a{};
       for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<uint64_t *>(ca.keys[b]);
@@ -299,11 +301,326 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
       a.shift = lo;
       a.width = width;
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                      launch_binning(rc.shape, &a, L.tiles, stream));
+                      launch_binning(rc.shape, false, &a, L.tiles, stream));
     }
   }
   ca.plan = plan;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_COPY, "copy", launch_copy(ca, stream_grid, stream));
+  return ONESWEEP_SUCCESS;
+}
+
+// ------------------------------------------------------------ segmented sort
+
+// Length limits of the LDS classes after applying the config: class c takes
+// lengths in (limit[c - 1], limit[c]]; an unused class repeats the previous
+// limit.
+onesweep_status_t segment_limits(const onesweep_config_t *cfg, uint32_t limit[kSegClasses]) {
+  uint32_t prev = 0;
+  for (int c = 0; c < kSegClasses; ++c) {
+    const int cap = lds_class_capacity(c);
+    const int v = cfg ? cfg->segment_limits[c] : 0;
+    if (v < -1 || v > cap)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "segment_limits[%d] = %d not in [-1, %d]", c, v,
+                  cap);
+    if (v != -1) prev = std::max(prev, static_cast<uint32_t>(v == 0 ? cap : v));
+    limit[c] = prev;
+  }
+  return ONESWEEP_SUCCESS;
+}
+
+// Temporary storage of a segmented sort. Bounds hold for any valid offsets:
+// a class whose lengths exceed L has at most n / (L + 1) segments, and the
+// large segments have at most floor(n / T) + (number of large segments) tiles.
+struct SegmentLayout {
+  uint32_t capacity[kSegClasses];
+  uint32_t max_large, max_tiles;
+  size_t plan, counters, lists[kSegClasses], tile_info, hist, status, tmp_keys, tmp_vals, total;
+  size_t status_words_per_place;
+};
+
+SegmentLayout segment_layout(size_t n, size_t num_segments, int key_bits, bool has_values,
+                             int places, size_t tile, const uint32_t limit[kSegClasses]) {
+  SegmentLayout L{};
+  uint32_t prev = 0;
+  for (int c = 0; c < kSegClasses; ++c) {
+    L.capacity[c] = limit[c] > prev
+                        ? static_cast<uint32_t>(std::min(num_segments, n / (size_t(prev) + 1)))
+                        : 0u;
+    prev = limit[c];
+  }
+  L.max_large = places > 0 ? static_cast<uint32_t>(std::min(num_segments, n / (size_t(prev) + 1)))
+                           : 0u;
+  L.max_tiles = L.max_large ? static_cast<uint32_t>(n / tile) + L.max_large : 0u;
+  L.status_words_per_place = static_cast<size_t>(L.max_tiles) * kRadix;
+  size_t off = 0;
+  L.plan = off;
+  off += kAlign;
+  L.counters = off;
+  off += kAlign;
+  for (int c = 0; c < kSegClasses; ++c) {
+    L.lists[c] = off;
+    off += align_up(sizeof(uint32_t) * L.capacity[c]);
+  }
+  L.tile_info = off;
+  off += align_up(sizeof(uint4) * L.max_tiles);
+  L.hist = off;
+  off += align_up(sizeof(uint32_t) * kRadix * places * static_cast<size_t>(L.max_large));
+  L.status = off;
+  off += align_up(sizeof(uint32_t) * L.status_words_per_place * places);
+  L.tmp_keys = off;
+  if (L.max_large) off += align_up(n * (key_bits / 8));
+  L.tmp_vals = off;
+  if (L.max_large && has_values) off += align_up(n * sizeof(uint32_t));
+  L.total = off;
+  return L;
+}
+
+// Resident workgroups per CU of each LDS class, cached per device.
+std::atomic<int> g_lds_occupancy[64][2][2][kSegClasses];
+
+onesweep_status_t lds_blocks_per_cu(int key_bits, bool has_values, int cls, int *blocks) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::atomic<int> *slot =
+      (dev >= 0 && dev < 64) ? &g_lds_occupancy[dev][key_bits == 64][has_values][cls] : nullptr;
+  if (slot && slot->load(std::memory_order_relaxed) > 0) {
+    *blocks = slot->load(std::memory_order_relaxed);
+    return ONESWEEP_SUCCESS;
+  }
+  int b = 0;
+  e = lds_sort_blocks_per_cu(key_bits, has_values, cls, &b);
+  if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+  if (b <= 0) b = 1;
+  if (slot) slot->store(b, std::memory_order_relaxed);
+  *blocks = b;
+  return ONESWEEP_SUCCESS;
+}
+
+onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *keys_in,
+                                void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                                bool has_values, size_t n, const uint32_t *seg_offsets,
+                                size_t num_segments, int key_bits, int begin_bit, int end_bit,
+                                const onesweep_config_t *cfg, hipStream_t stream) {
+  g_error[0] = '\0';
+  onesweep_status_t st = check_common(temp_bytes, n, key_bits, begin_bit, end_bit);
+  if (st) return st;
+  if (num_segments >= kMaxN)
+    return fail(ONESWEEP_ERROR_TOO_LARGE, "num_segments = %zu is not below 2^30", num_segments);
+  if (num_segments == 0 && n != 0)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "%zu keys but no segment", n);
+  Resolved rc;
+  if ((st = resolve(key_bits, has_values, cfg, &rc, true))) return st;
+  uint32_t limit[kSegClasses];
+  if ((st = segment_limits(cfg, limit))) return st;
+  const int places = num_places(begin_bit, end_bit);
+  const size_t tile = static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
+  const SegmentLayout L =
+      segment_layout(n, num_segments, key_bits, has_values, places, tile, limit);
+  if (d_temp == nullptr) {
+    *temp_bytes = L.total;
+    return ONESWEEP_SUCCESS;
+  }
+  if (rc.trace) rc.trace->count = 0;
+  if (n == 0) return ONESWEEP_SUCCESS;
+  if (*temp_bytes < L.total)
+    return fail(ONESWEEP_ERROR_INSUFFICIENT_TEMP, "temp storage %zu bytes, need %zu",
+                *temp_bytes, L.total);
+  const size_t kb = static_cast<size_t>(key_bits / 8);
+  if (!keys_in || !keys_out) return fail(ONESWEEP_ERROR_INVALID_VALUE, "NULL key pointer");
+  if (has_values && (!vals_in || !vals_out))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "NULL value pointer");
+  if (!seg_offsets) return fail(ONESWEEP_ERROR_INVALID_VALUE, "NULL segment offsets");
+  if ((reinterpret_cast<uintptr_t>(d_temp) & (kAlign - 1)) != 0)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_temp is not 256-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(keys_in) | reinterpret_cast<uintptr_t>(keys_out)) & (kb - 1))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "key pointers not %zu-byte aligned", kb);
+  if ((has_values &&
+       ((reinterpret_cast<uintptr_t>(vals_in) | reinterpret_cast<uintptr_t>(vals_out)) & 3u)) ||
+      (reinterpret_cast<uintptr_t>(seg_offsets) & 3u))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "value or offset pointers not 4-byte aligned");
+  const bool keys_alias = keys_in == keys_out;
+  if (!keys_alias && ranges_overlap(keys_in, n * kb, keys_out, n * kb))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "key input and output partially overlap");
+  bool vals_alias = false;
+  if (has_values) {
+    vals_alias = vals_in == vals_out;
+    if (!vals_alias && ranges_overlap(vals_in, n * 4, vals_out, n * 4))
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "value input and output partially overlap");
+    if (ranges_overlap(keys_in, n * kb, vals_out, n * 4) ||
+        ranges_overlap(keys_out, n * kb, vals_in, n * 4) ||
+        ranges_overlap(keys_out, n * kb, vals_out, n * 4))
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "key and value buffers overlap");
+  }
+  const size_t off_bytes = (num_segments + 1) * sizeof(uint32_t);
+  if (ranges_overlap(seg_offsets, off_bytes, keys_out, n * kb) ||
+      (has_values && ranges_overlap(seg_offsets, off_bytes, vals_out, n * 4)) ||
+      ranges_overlap(seg_offsets, off_bytes, d_temp, L.total))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "segment offsets overlap an output or temp storage");
+  if (ranges_overlap(d_temp, L.total, keys_in, n * kb) ||
+      ranges_overlap(d_temp, L.total, keys_out, n * kb) ||
+      (has_values && (ranges_overlap(d_temp, L.total, vals_in, n * 4) ||
+                      ranges_overlap(d_temp, L.total, vals_out, n * 4))))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp storage overlaps keys or values");
+  const bool alias = keys_alias || vals_alias;
+
+  int cus = 0;
+  if ((st = device_cus(&cus))) return st;
+  const uint32_t stream_grid = static_cast<uint32_t>(cus) * 4u;
+  Tracer tr(rc.trace, stream);
+  char *temp = static_cast<char *>(d_temp);
+
+  if (places == 0) {  // empty bit range: every segment is already in order
+    // The offsets are not read; the status word reads 0.
+    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "clear",
+                    launch_fill_zero(temp + L.plan, kAlign, 1, stream));
+    CopyArgs ca{};
+    ca.keys[kBufIn] = const_cast<void *>(keys_in);
+    ca.keys[kBufOut] = keys_out;
+    ca.vals[kBufIn] = const_cast<uint32_t *>(vals_in);
+    ca.vals[kBufOut] = vals_out;
+    ca.n = static_cast<uint32_t>(n);
+    ca.key_bytes = static_cast<int>(kb);
+    if (!alias || (has_values && keys_alias != vals_alias))
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_COPY, "copy", launch_copy(ca, stream_grid, stream));
+    return ONESWEEP_SUCCESS;
+  }
+
+  SegmentPlan *plan = reinterpret_cast<SegmentPlan *>(temp + L.plan);
+  uint32_t *counters = reinterpret_cast<uint32_t *>(temp + L.counters);
+  uint4 *tile_info = reinterpret_cast<uint4 *>(temp + L.tile_info);
+  uint32_t *hist = reinterpret_cast<uint32_t *>(temp + L.hist);
+  uint32_t *status = reinterpret_cast<uint32_t *>(temp + L.status);
+
+  ClassifyArgs ca{};
+  ca.offsets = seg_offsets;
+  ca.num_segments = static_cast<uint32_t>(num_segments);
+  ca.n = static_cast<uint32_t>(n);
+  for (int c = 0; c < kSegClasses; ++c) {
+    ca.limit[c] = limit[c];
+    ca.capacity[c] = L.capacity[c];
+    ca.lists[c] = reinterpret_cast<uint32_t *>(temp + L.lists[c]);
+  }
+  ca.max_large = L.max_large;
+  ca.max_tiles = L.max_tiles;
+  ca.tile_items = static_cast<uint32_t>(tile);
+  ca.tile_info = tile_info;
+  ca.tile_counters = counters;
+  ca.plan = plan;
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_CLASSIFY, "classify", launch_classify(ca, stream));
+
+  for (int c = 0; c < kSegClasses; ++c) {
+    if (L.capacity[c] == 0) continue;
+    int per_cu = 0;
+    if ((st = lds_blocks_per_cu(key_bits, has_values, c, &per_cu))) return st;
+    LdsSortArgs la{};
+    la.keys_in = keys_in;
+    la.keys_out = keys_out;
+    la.vals_in = vals_in;
+    la.vals_out = vals_out;
+    la.offsets = seg_offsets;
+    la.list = ca.lists[c];
+    la.plan = plan;
+    la.cls = c;
+    la.begin_bit = begin_bit;
+    la.end_bit = end_bit;
+    la.places = places;
+    const uint32_t grid =
+        std::min<uint32_t>(L.capacity[c], static_cast<uint32_t>(cus) * static_cast<uint32_t>(per_cu));
+    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_LDS_SORT, "lds sort",
+                    launch_lds_sort(key_bits, has_values, la, grid, stream));
+  }
+  if (L.max_large == 0) return ONESWEEP_SUCCESS;
+
+  SegmentClearArgs za{};
+  za.status = status;
+  za.status_words_per_place = L.status_words_per_place;
+  za.hist = hist;
+  za.plan = plan;
+  za.places = places;
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "segment clear",
+                  launch_segment_clear(za, stream_grid, stream));
+  SegmentHistArgs ha{};
+  ha.keys = keys_in;
+  ha.tile_info = tile_info;
+  ha.hist = hist;
+  ha.plan = plan;
+  ha.begin_bit = begin_bit;
+  ha.end_bit = end_bit;
+  ha.places = places;
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "segment histogram",
+                  launch_segment_histogram(key_bits, ha, std::min(L.max_tiles, stream_grid),
+                                           stream));
+  const uint32_t rows = L.max_large * static_cast<uint32_t>(places);
+  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_SCAN, "segment scan",
+                  launch_segment_scan(hist, plan, places,
+                                      std::min((rows + 3u) / 4u, stream_grid), stream));
+
+  // Static routing of the large segments' passes: with the input aliasing
+  // the output the first pass must not write the output, so the passes go
+  // in -> tmp -> out -> tmp ... and an odd count ends with a copy; otherwise
+  // the alternation is chosen so that the last pass writes the output.
+  void *kbuf[3] = {const_cast<void *>(keys_in), keys_out, temp + L.tmp_keys};
+  uint32_t *vbuf[3] = {const_cast<uint32_t *>(vals_in), vals_out,
+                       has_values ? reinterpret_cast<uint32_t *>(temp + L.tmp_vals) : nullptr};
+  auto buffer_after = [&](int passes_done) -> int {
+    if (passes_done == 0) return kBufIn;
+    if (alias) return (passes_done & 1) ? kBufTmp : kBufOut;
+    return ((places - passes_done) & 1) ? kBufTmp : kBufOut;
+  };
+  SegmentTiles seg{};
+  seg.tile_info = tile_info;
+  seg.bin_offsets = hist;
+  seg.plan = plan;
+  seg.places = places;
+  for (int j = 0; j < places; ++j) {
+    const int lo = begin_bit + j * kRadixBits;
+    const int width = (lo + kRadixBits <= end_bit) ? kRadixBits : end_bit - lo;
+    const int from = buffer_after(j), to = buffer_after(j + 1);
+    if (key_bits == 32) {
+      BinningArgs<uint32_t> a{};
+      a.keys[kBufIn] = static_cast<uint32_t *>(kbuf[from]);
+      a.keys[kBufOut] = static_cast<uint32_t *>(kbuf[to]);
+      a.vals[kBufIn] = vbuf[from];
+      a.vals[kBufOut] = vbuf[to];
+      a.status = status + j * L.status_words_per_place;
+      a.tile_counter = counters + j;
+      a.seg = seg;
+      a.n = static_cast<uint32_t>(n);
+      a.place = j;
+      a.shift = lo;
+      a.width = width;
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "segment binning",
+                      launch_binning(rc.shape, true, &a, L.max_tiles, stream));
+    } else {
+      BinningArgs<uint64_t> a{};
+      a.keys[kBufIn] = static_cast<uint64_t *>(kbuf[from]);
+      a.keys[kBufOut] = static_cast<uint64_t *>(kbuf[to]);
+      a.vals[kBufIn] = vbuf[from];
+      a.vals[kBufOut] = vbuf[to];
+      a.status = status + j * L.status_words_per_place;
+      a.tile_counter = counters + j;
+      a.seg = seg;
+      a.n = static_cast<uint32_t>(n);
+      a.place = j;
+      a.shift = lo;
+      a.width = width;
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "segment binning",
+                      launch_binning(rc.shape, true, &a, L.max_tiles, stream));
+    }
+  }
+  if (buffer_after(places) != kBufOut) {
+    SegmentCopyArgs pa{};
+    pa.keys_src = kbuf[kBufTmp];
+    pa.keys_dst = keys_out;
+    pa.vals_src = vbuf[kBufTmp];
+    pa.vals_dst = vals_out;
+    pa.tile_info = tile_info;
+    pa.plan = plan;
+    pa.key_bytes = static_cast<int>(kb);
+    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_COPY, "segment copy",
+                    launch_segment_copy(pa, std::min(L.max_tiles, stream_grid), stream));
+  }
   return ONESWEEP_SUCCESS;
 }
 
@@ -432,7 +749,7 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.shift = shift;
     a.width = width;
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                    launch_binning(rc.shape, &a, tiles, s));
+                    launch_binning(rc.shape, false, &a, tiles, s));
   } else {
     BinningArgs<uint64_t> a{};
     a.keys[kBufIn] = static_cast<uint64_t *>(const_cast<void *>(d_src_keys));
@@ -448,9 +765,23 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.shift = shift;
     a.width = width;
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                    launch_binning(rc.shape, &a, tiles, s));
+                    launch_binning(rc.shape, false, &a, tiles, s));
   }
   return ONESWEEP_SUCCESS;
+}
+
+onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
+                                         const void *d_keys_in, void *d_keys_out,
+                                         const uint32_t *d_vals_in, uint32_t *d_vals_out,
+                                         size_t n, const uint32_t *d_seg_offsets,
+                                         size_t num_segments, int key_bits, int begin_bit,
+                                         int end_bit, int stable, const onesweep_config_t *cfg,
+                                         onesweep_stream_t stream) {
+  (void)stable;
+  const bool has_values = d_vals_in != nullptr || d_vals_out != nullptr;
+  return segments_impl(d_temp, temp_bytes, d_keys_in, d_keys_out, d_vals_in, d_vals_out,
+                       has_values, n, d_seg_offsets, num_segments, key_bits, begin_bit, end_bit,
+                       cfg, reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t onesweep_tile_items(int key_bits, int has_values, const onesweep_config_t *cfg) {

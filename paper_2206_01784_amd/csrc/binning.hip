@@ -58,7 +58,9 @@ constexpr int binning_waves_per_eu() {
   return (kIpt * sizeof(K)) <= 32 ? 8 : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
 }
 
-template <typename K, bool kVals, int kBlock, int kIpt, int kRank>
+// kSeg: the tiles belong to the large segments of a segmented sort (each
+// segment its own chained scan and bin offsets); otherwise to one sequence.
+template <typename K, bool kVals, int kBlock, int kIpt, int kRank, bool kSeg>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(binning_waves_per_eu<K, kIpt>())))
     binning_kernel(BinningArgs<K> a) {
@@ -101,6 +103,12 @@ __global__ void __launch_bounds__(kBlock)
   const uint32_t mask = (1u << width) - 1u;
   const uint32_t n = a.n;
 
+  // The segmented grid is sized for the most tiles the offsets could need;
+  // workgroups beyond the actual count leave before taking a tile id, so the
+  // ids handed out are exactly 0 .. tiles - 1.
+  if constexpr (kSeg) {
+    if (blockIdx.x >= a.seg.plan->large_tiles) return;
+  }
   {
     uint4 *z = reinterpret_cast<uint4 *>(s_rank);
     for (int i = tid; i < static_cast<int>(kRankBytes / 16); i += kBlock)
@@ -109,8 +117,24 @@ __global__ void __launch_bounds__(kBlock)
   if (tid == 0) s_tile = atomicAdd(a.tile_counter, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
-  const uint32_t tile_base = tile * static_cast<uint32_t>(kTile);
-  const uint32_t tile_count = min(n - tile_base, static_cast<uint32_t>(kTile));
+  uint32_t tile_base, tile_count, bin_base;
+  const uint32_t *bin_offsets;
+  bool first;
+  if constexpr (kSeg) {
+    const uint4 info = a.seg.tile_info[tile];
+    tile_base = info.x;
+    tile_count = info.y;
+    bin_base = info.z;
+    first = info.x == info.z;
+    bin_offsets = a.seg.bin_offsets + (static_cast<size_t>(info.w) * a.seg.places + a.place) * kRadix;
+  } else {
+    tile_base = tile * static_cast<uint32_t>(kTile);
+    tile_count = min(n - tile_base, static_cast<uint32_t>(kTile));
+    bin_base = 0u;
+    first = tile == 0u;
+    bin_offsets = a.bin_offsets;
+  }
+  const uint32_t tile_end = tile_base + tile_count;
   const bool full = tile_count == static_cast<uint32_t>(kTile);
 
   // 1. Load. Lanes past the end get an all-ones key: its digit is the
@@ -125,7 +149,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t idx = wave_base + i * kWave;
-      key[i] = idx < n ? src[idx] : static_cast<K>(~static_cast<K>(0));
+      key[i] = idx < tile_end ? src[idx] : static_cast<K>(~static_cast<K>(0));
     }
   }
 
@@ -185,9 +209,10 @@ __global__ void __launch_bounds__(kBlock)
     }
     published = total;
     if (!full && static_cast<uint32_t>(tid) == mask) published -= kTile - tile_count;
-    // 4a. Publish this tile's count (tile 0's count is already its prefix).
+    // 4a. Publish this tile's count (a first tile's count is already its
+    // prefix).
     store_status(&a.status[static_cast<size_t>(tile) * kRadix + tid],
-                 (tile == 0u ? kFlagG : kFlagL) | published);
+                 (first ? kFlagG : kFlagL) | published);
     uint32_t incl = total;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -219,7 +244,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t idx = wave_base + i * kWave;
-      val[i] = (full || idx < n) ? vsrc[idx] : 0u;
+      val[i] = (full || idx < tile_end) ? vsrc[idx] : 0u;
     }
   }
 
@@ -228,9 +253,9 @@ __global__ void __launch_bounds__(kBlock)
   // trip reads a window of kLookback predecessors at once; tiles before the
   // first one read as an inclusive prefix of zero.
   if (tid < kRadix) {
-    const uint32_t bin_start = a.bin_offsets[tid];
+    const uint32_t bin_start = bin_base + bin_offsets[tid];
     uint32_t exclusive = 0u;
-    if (tile != 0u) {
+    if (!first) {
       int pred = static_cast<int>(tile) - 1;
       while (true) {
         uint32_t s[kLookback];
@@ -332,12 +357,32 @@ __global__ void __launch_bounds__(kBlock)
   X(uint64_t, true, 512, 12, 1)       \
   X(uint64_t, true, 1024, 8, 1)
 
-bool binning_shape_supported(const BinningShape &s) {
-#define ONESWEEP_MATCH(K, V, B, I, R)                                                  \
-  if (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I && \
-      s.rank == R)                                                                          \
-    return true;
-  ONESWEEP_BINNING_SHAPES(ONESWEEP_MATCH)
+// Shapes also built for the large segments of a segmented sort.
+#define ONESWEEP_SEGMENT_BINNING_SHAPES(X) \
+  X(uint32_t, false, 256, 16, 0)           \
+  X(uint32_t, false, 512, 16, 0)           \
+  X(uint32_t, false, 1024, 8, 0)           \
+  X(uint32_t, true, 256, 16, 0)            \
+  X(uint32_t, true, 512, 16, 0)            \
+  X(uint32_t, true, 1024, 8, 0)            \
+  X(uint64_t, false, 256, 16, 0)           \
+  X(uint64_t, false, 512, 8, 0)            \
+  X(uint64_t, false, 1024, 8, 0)           \
+  X(uint64_t, true, 256, 16, 0)            \
+  X(uint64_t, true, 512, 8, 0)             \
+  X(uint64_t, true, 1024, 8, 0)
+
+#define ONESWEEP_SHAPE_IS(K, V, B, I, R) \
+  (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I && s.rank == R)
+
+bool binning_shape_supported(const BinningShape &s, bool segmented) {
+#define ONESWEEP_MATCH(K, V, B, I, R) \
+  if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) return true;
+  if (segmented) {
+    ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_MATCH)
+  } else {
+    ONESWEEP_BINNING_SHAPES(ONESWEEP_MATCH)
+  }
 #undef ONESWEEP_MATCH
   return false;
 }
@@ -349,16 +394,23 @@ BinningShape binning_default_shape(int key_bits, bool has_values) {
   return BinningShape{32, false, 1024, 8, kRankBallot};
 }
 
-hipError_t launch_binning(const BinningShape &s, const void *args, uint32_t grid,
-                          hipStream_t stream) {
-#define ONESWEEP_LAUNCH(K, V, B, I, R)                                                       \
-  if (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I &&  \
-      s.rank == R) {                                                                          \
-    hipLaunchKernelGGL((binning_kernel<K, V, B, I, R>), dim3(grid), dim3(B), 0, stream,        \
-                       *static_cast<const BinningArgs<K> *>(args));                           \
-    return hipGetLastError();                                                                 \
+hipError_t launch_binning(const BinningShape &s, bool segmented, const void *args,
+                          uint32_t grid, hipStream_t stream) {
+#define ONESWEEP_LAUNCH(K, V, B, I, R, SEG)                                             \
+  if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) {                                                \
+    hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, SEG>), dim3(grid), dim3(B), 0, stream, \
+                       *static_cast<const BinningArgs<K> *>(args));                      \
+    return hipGetLastError();                                                            \
   }
-  ONESWEEP_BINNING_SHAPES(ONESWEEP_LAUNCH)
+#define ONESWEEP_LAUNCH_FLAT(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, false)
+#define ONESWEEP_LAUNCH_SEG(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, true)
+  if (segmented) {
+    ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_LAUNCH_SEG)
+  } else {
+    ONESWEEP_BINNING_SHAPES(ONESWEEP_LAUNCH_FLAT)
+  }
+#undef ONESWEEP_LAUNCH_SEG
+#undef ONESWEEP_LAUNCH_FLAT
 #undef ONESWEEP_LAUNCH
   return hipErrorInvalidValue;
 }

@@ -38,6 +38,33 @@ struct PassPlan {
 };
 static_assert(sizeof(PassPlan) <= 256, "plan fits one 256-byte slot");
 
+// Segmented sort (independent stable sorts of the ranges
+// [offsets[s], offsets[s + 1])). The classify kernel sorts the segments into
+// classes by length: three classes sorted whole inside one workgroup's LDS
+// and a "large" class whose segments are cut into binning tiles. Each large
+// segment is an Onesweep sort of its own, with its own histograms, bin offsets
+// and chained scan; the tiles of all large segments are enumerated together so
+// one binning launch per digit place covers them all.
+constexpr int kSegClasses = 3;  // LDS-sorted classes; class kSegClasses is "large"
+
+struct SegmentPlan {
+  uint32_t error;                      // 1: offsets invalid, nothing is sorted
+  uint32_t count[kSegClasses + 1];     // segments per class (last: large)
+  uint32_t large_tiles;                // binning tiles of all large segments
+  uint32_t pad[58];
+};
+static_assert(sizeof(SegmentPlan) == 256, "one 256-byte slot");
+
+// One binning tile of a large segment: x = first key, y = keys in the tile,
+// z = first key of the segment, w = index of the segment among large ones.
+// A tile with x == z starts its segment's chained scan.
+struct SegmentTiles {
+  const uint4 *tile_info;       // [tiles]
+  const uint32_t *bin_offsets;  // [large][places][256] exclusive sums within the segment
+  const SegmentPlan *plan;
+  int places;
+};
+
 template <typename K>
 struct BinningArgs {
   K *keys[3];                  // in, out, tmp (in is only read)
@@ -46,6 +73,7 @@ struct BinningArgs {
   uint32_t *status;            // [tiles][256] status words of this place
   uint32_t *tile_counter;      // dynamic tile ids of this place
   const PassPlan *plan;        // NULL: run unconditionally in -> out
+  SegmentTiles seg;            // segmented sort only
   uint32_t n;
   int place;
   int shift;

@@ -22,12 +22,14 @@ struct BinningShape {
   int rank;
 };
 
-bool binning_shape_supported(const BinningShape &s);
+// `segmented`: the variant whose tiles are those of a segmented sort's large
+// segments (BinningArgs::seg); fewer shapes are built for it.
+bool binning_shape_supported(const BinningShape &s, bool segmented);
 BinningShape binning_default_shape(int key_bits, bool has_values);
 
 // `args` points to BinningArgs<uint32_t> or BinningArgs<uint64_t>.
-hipError_t launch_binning(const BinningShape &s, const void *args, uint32_t grid,
-                          hipStream_t stream);
+hipError_t launch_binning(const BinningShape &s, bool segmented, const void *args,
+                          uint32_t grid, hipStream_t stream);
 
 // Histogram of all places (phase 1), persistent tile-cyclic grid.
 constexpr int kHistBlock = 256;
@@ -54,5 +56,77 @@ hipError_t launch_copy(const CopyArgs &a, uint32_t grid, hipStream_t stream);
 // Zero `bytes` (a multiple of 4) bytes at `p` with a kernel, so that the
 // enqueued sequence stays free of memset nodes.
 hipError_t launch_fill_zero(void *p, size_t bytes, uint32_t grid, hipStream_t stream);
+
+// ---------------------------------------------------------------- segmented sort
+// Class c (< kSegClasses) takes the non-empty segments with
+// limit[c - 1] < length <= limit[c] (limit[-1] = 0); longer ones are large.
+struct ClassifyArgs {
+  const uint32_t *offsets;
+  uint32_t num_segments;
+  uint32_t n;
+  uint32_t limit[kSegClasses];
+  uint32_t capacity[kSegClasses];  // entries of lists[c]
+  uint32_t *lists[kSegClasses];    // segment ids per LDS class
+  uint32_t max_large;
+  uint32_t max_tiles;
+  uint32_t tile_items;             // binning tile of the large segments
+  uint4 *tile_info;                // [max_tiles]
+  uint32_t *tile_counters;         // kMaxPlaces words, cleared
+  SegmentPlan *plan;
+};
+hipError_t launch_classify(const ClassifyArgs &a, hipStream_t stream);
+
+struct SegmentClearArgs {
+  uint32_t *status;
+  size_t status_words_per_place;
+  uint32_t *hist;
+  const SegmentPlan *plan;
+  int places;
+};
+hipError_t launch_segment_clear(const SegmentClearArgs &a, uint32_t grid, hipStream_t stream);
+
+struct SegmentHistArgs {
+  const void *keys;
+  const uint4 *tile_info;
+  uint32_t *hist;  // [large][places][256]
+  const SegmentPlan *plan;
+  int begin_bit;
+  int end_bit;
+  int places;
+};
+hipError_t launch_segment_histogram(int key_bits, const SegmentHistArgs &a, uint32_t grid,
+                                    hipStream_t stream);
+hipError_t launch_segment_scan(uint32_t *hist, const SegmentPlan *plan, int places, uint32_t grid,
+                               hipStream_t stream);
+
+struct SegmentCopyArgs {
+  const void *keys_src;
+  void *keys_dst;
+  const uint32_t *vals_src;
+  uint32_t *vals_dst;
+  const uint4 *tile_info;
+  const SegmentPlan *plan;
+  int key_bytes;
+};
+hipError_t launch_segment_copy(const SegmentCopyArgs &a, uint32_t grid, hipStream_t stream);
+
+struct LdsSortArgs {
+  const void *keys_in;
+  void *keys_out;
+  const uint32_t *vals_in;
+  uint32_t *vals_out;
+  const uint32_t *offsets;
+  const uint32_t *list;  // segment ids of this class
+  const SegmentPlan *plan;
+  int cls;
+  int begin_bit;
+  int end_bit;
+  int places;
+};
+int lds_class_capacity(int cls);
+int lds_class_block(int cls);
+hipError_t lds_sort_blocks_per_cu(int key_bits, bool has_values, int cls, int *blocks);
+hipError_t launch_lds_sort(int key_bits, bool has_values, const LdsSortArgs &a, uint32_t grid,
+                           hipStream_t stream);
 
 }  // namespace onesweep

@@ -1,0 +1,460 @@
+// Segmented sort: many independent stable sorts, one per range
+// [offsets[s], offsets[s + 1]), enqueued as a fixed sequence of kernels (so the
+// whole batch can be captured in one HIP graph) and driven by device-side
+// offsets, so the host never learns the segment lengths.
+//
+//  - classify: one workgroup validates the offsets and assigns every
+//    non-empty segment to a class by length: three classes small enough to be
+//    sorted inside one workgroup's LDS (64, 256 or 1024 threads, 8 keys per
+//    thread) and a "large" class. Each large segment is cut into binning tiles
+//    whose descriptors are written in segment order.
+//  - LDS sort: one workgroup per segment loads it once, runs the LSD passes
+//    over 8-bit digits in LDS with the same wave64 multi-split ranking as the
+//    binning kernel, and writes it once.
+//  - large segments: an Onesweep sort per segment (Section 3): histograms of
+//    every place per segment, their exclusive sums, and one binning launch per
+//    place over the tiles of all large segments, each segment its own chained
+//    scan.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace onesweep {
+
+// ---------------------------------------------------------------- classify
+constexpr int kClassifyBlock = 1024;
+
+__global__ void __launch_bounds__(kClassifyBlock) classify_kernel(ClassifyArgs a) {
+  constexpr int kWaves = kClassifyBlock / kWave;
+  constexpr int kQ = kSegClasses + 2;  // per-class counts, then tiles
+  __shared__ uint32_t s_wave[kWaves][kQ];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  if (tid < kMaxPlaces) a.tile_counters[tid] = 0u;
+
+  uint32_t run[kQ];
+#pragma unroll
+  for (int c = 0; c < kQ; ++c) run[c] = 0u;
+  bool bad = false;
+  const uint32_t T = a.tile_items;
+
+  for (uint32_t base = 0; base < a.num_segments; base += kClassifyBlock) {
+    const uint32_t s = base + tid;
+    uint32_t cls = kQ, tiles = 0u, lo = 0u, len = 0u;
+    if (s < a.num_segments) {
+      lo = a.offsets[s];
+      const uint32_t hi = a.offsets[s + 1];
+      if (hi < lo || hi > a.n) {
+        bad = true;
+      } else {
+        len = hi - lo;
+        if (len > 0u) {
+          cls = kSegClasses;
+          for (int c = kSegClasses - 1; c >= 0; --c)
+            if (len <= a.limit[c]) cls = c;
+          if (cls == kSegClasses) tiles = (len + T - 1u) / T;
+        }
+      }
+    }
+    // Block-wide exclusive prefix of the class flags and of the tile counts.
+    uint32_t rank = 0u;
+#pragma unroll
+    for (int c = 0; c <= kSegClasses; ++c) {
+      const uint64_t m = __builtin_amdgcn_ballot_w64(cls == static_cast<uint32_t>(c));
+      if (cls == static_cast<uint32_t>(c)) rank = count_below(m);
+      if (lane == 0) s_wave[wave][c] = static_cast<uint32_t>(__popcll(m));
+    }
+    uint32_t incl = tiles;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl += t;
+    }
+    if (lane == kWave - 1) s_wave[wave][kQ - 1] = incl;
+    __syncthreads();
+    uint32_t pre[kQ];
+#pragma unroll
+    for (int c = 0; c < kQ; ++c) {
+      uint32_t before = 0u, all = 0u;
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t v = s_wave[w][c];
+        if (w < wave) before += v;
+        all += v;
+      }
+      pre[c] = run[c] + before;
+      run[c] += all;
+    }
+    if (cls < static_cast<uint32_t>(kSegClasses)) {
+      const uint32_t idx = pre[cls] + rank;
+      if (idx < a.capacity[cls]) a.lists[cls][idx] = s;
+    } else if (cls == static_cast<uint32_t>(kSegClasses)) {
+      const uint32_t li = pre[kSegClasses] + rank;
+      const uint32_t first = pre[kQ - 1] + incl - tiles;
+      for (uint32_t k = 0; k < tiles; ++k) {
+        if (first + k >= a.max_tiles) break;  // only reachable with invalid offsets
+        const uint32_t b = lo + k * T;
+        a.tile_info[first + k] = make_uint4(b, min(T, len - k * T), lo, li);
+      }
+    }
+    __syncthreads();  // s_wave is rewritten by the next chunk
+  }
+  if (tid == 0) {
+    if (a.offsets[0] != 0u || a.offsets[a.num_segments] != a.n) bad = true;
+    if (run[kSegClasses] > a.max_large || run[kQ - 1] > a.max_tiles) bad = true;
+    for (int c = 0; c < kSegClasses; ++c)
+      if (run[c] > a.capacity[c]) bad = true;
+  }
+  const int invalid = __syncthreads_or(bad);
+  if (tid == 0) {
+    SegmentPlan p;
+    p.error = invalid ? 1u : 0u;
+    for (int c = 0; c <= kSegClasses; ++c) p.count[c] = invalid ? 0u : run[c];
+    p.large_tiles = invalid ? 0u : run[kQ - 1];
+    for (int i = 0; i < 58; ++i) p.pad[i] = 0u;
+    *a.plan = p;
+  }
+}
+
+hipError_t launch_classify(const ClassifyArgs &a, hipStream_t stream) {
+  hipLaunchKernelGGL(classify_kernel, dim3(1), dim3(kClassifyBlock), 0, stream, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- clear
+// Clears the status rows of the tiles that exist and the histograms of the
+// large segments that exist, sized from the plan on the device.
+__global__ void __launch_bounds__(256) segment_clear_kernel(SegmentClearArgs a) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  const size_t first = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+  const size_t status_vecs = static_cast<size_t>(a.plan->large_tiles) * (kRadix / 4);
+  for (int j = 0; j < a.places; ++j) {
+    uint4 *row = reinterpret_cast<uint4 *>(a.status + j * a.status_words_per_place);
+    for (size_t i = first; i < status_vecs; i += stride) row[i] = zero;
+  }
+  const size_t hist_vecs =
+      static_cast<size_t>(a.plan->count[kSegClasses]) * a.places * (kRadix / 4);
+  uint4 *hist = reinterpret_cast<uint4 *>(a.hist);
+  for (size_t i = first; i < hist_vecs; i += stride) hist[i] = zero;
+}
+
+hipError_t launch_segment_clear(const SegmentClearArgs &a, uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(segment_clear_kernel, dim3(grid), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- histogram
+// Digit counts of every place per large segment. Workgroups take tiles
+// cyclically, count into LDS (kCopies interleaved copies, as in the upfront
+// histogram) and add the non-zero counts to their segment's histograms.
+template <typename K>
+__global__ void __launch_bounds__(256) segment_histogram_kernel(SegmentHistArgs a) {
+  constexpr int kMaxP = static_cast<int>(sizeof(K));
+  constexpr int kCopies = 4;
+  __shared__ uint32_t s_hist[kMaxP * kRadix * kCopies];
+  const K *keys = static_cast<const K *>(a.keys);
+  const int tid = threadIdx.x;
+  const int places = a.places;
+  int shifts[kMaxP];
+  uint32_t masks[kMaxP];
+#pragma unroll
+  for (int j = 0; j < kMaxP; ++j) {
+    const int lo = a.begin_bit + j * kRadixBits;
+    const int hi = min(lo + kRadixBits, a.end_bit);
+    shifts[j] = j < places ? lo : 0;
+    masks[j] = j < places ? ((1u << (hi - lo)) - 1u) : 0u;
+  }
+  uint32_t *my_hist = s_hist + (tid % kCopies);
+  const uint32_t tiles = a.plan->large_tiles;
+  for (int i = tid; i < places * kRadix * kCopies; i += 256) s_hist[i] = 0u;
+  __syncthreads();
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const uint4 info = a.tile_info[t];
+    for (uint32_t i = tid; i < info.y; i += 256) {
+      const K k = keys[info.x + i];
+#pragma unroll
+      for (int j = 0; j < kMaxP; ++j)
+        if (j < places)
+          atomicAdd(&my_hist[(j * kRadix + (static_cast<uint32_t>(k >> shifts[j]) & masks[j])) *
+                             kCopies],
+                    1u);
+    }
+    __syncthreads();
+    uint32_t *dst = a.hist + static_cast<size_t>(info.w) * places * kRadix;
+    for (int i = tid; i < places * kRadix; i += 256) {
+      uint32_t c = 0u;
+#pragma unroll
+      for (int k = 0; k < kCopies; ++k) {
+        c += s_hist[i * kCopies + k];
+        s_hist[i * kCopies + k] = 0u;
+      }
+      if (c != 0u) atomicAdd(&dst[i], c);
+    }
+    __syncthreads();
+  }
+}
+
+// Exclusive sum of every (large segment, place) histogram row, in place: one
+// wavefront per row of 256 counts.
+__global__ void __launch_bounds__(256) segment_scan_kernel(uint32_t *hist,
+                                                            const SegmentPlan *plan, int places) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  const uint32_t waves = gridDim.x * (256 / kWave);
+  const uint32_t rows = plan->count[kSegClasses] * static_cast<uint32_t>(places);
+  for (uint32_t row = wave; row < rows; row += waves) {
+    uint4 *p = reinterpret_cast<uint4 *>(hist + static_cast<size_t>(row) * kRadix) + lane;
+    const uint4 v = *p;
+    const uint32_t s1 = v.x, s2 = s1 + v.y, s3 = s2 + v.z, total = s3 + v.w;
+    uint32_t incl = total;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl += t;
+    }
+    const uint32_t e = incl - total;
+    *p = make_uint4(e, e + s1, e + s2, e + s3);
+  }
+}
+
+hipError_t launch_segment_histogram(int key_bits, const SegmentHistArgs &a, uint32_t grid,
+                                    hipStream_t stream) {
+  if (key_bits == 32)
+    hipLaunchKernelGGL(segment_histogram_kernel<uint32_t>, dim3(grid), dim3(256), 0, stream, a);
+  else
+    hipLaunchKernelGGL(segment_histogram_kernel<uint64_t>, dim3(grid), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_scan(uint32_t *hist, const SegmentPlan *plan, int places, uint32_t grid,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(segment_scan_kernel, dim3(grid), dim3(256), 0, stream, hist, plan, places);
+  return hipGetLastError();
+}
+
+// Copy of the large segments' keys (and values) from the temporary buffer to
+// the output, for an odd number of passes with the input aliasing the output.
+__global__ void __launch_bounds__(256) segment_copy_kernel(SegmentCopyArgs a) {
+  const uint32_t tiles = a.plan->large_tiles;
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const uint4 info = a.tile_info[t];
+    if (a.key_bytes == 4) {
+      const uint32_t *s = static_cast<const uint32_t *>(a.keys_src);
+      uint32_t *d = static_cast<uint32_t *>(a.keys_dst);
+      for (uint32_t i = threadIdx.x; i < info.y; i += 256) d[info.x + i] = s[info.x + i];
+    } else {
+      const uint64_t *s = static_cast<const uint64_t *>(a.keys_src);
+      uint64_t *d = static_cast<uint64_t *>(a.keys_dst);
+      for (uint32_t i = threadIdx.x; i < info.y; i += 256) d[info.x + i] = s[info.x + i];
+    }
+    if (a.vals_src != nullptr && a.vals_dst != nullptr && a.vals_src != a.vals_dst)
+      for (uint32_t i = threadIdx.x; i < info.y; i += 256)
+        a.vals_dst[info.x + i] = a.vals_src[info.x + i];
+  }
+}
+
+hipError_t launch_segment_copy(const SegmentCopyArgs &a, uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(segment_copy_kernel, dim3(grid), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- LDS sort
+// One workgroup sorts one segment of at most kBlock * kIpt keys at a time
+// (workgroups take the class's segments cyclically). The key at slot
+// q = wave * 64 * kIpt + 64 * i + lane sits in register i of that lane, so
+// (wave, i, lane) order is slot order and the multi-split ranks are stable.
+// Per digit place: rank every key among the earlier keys with its digit,
+// turn the per-wave digit counts into positions, scatter the keys to their
+// positions in LDS and read them back in slot order. Batches of 64 slots
+// that start past the segment's end take no part; the last partial batch is
+// padded with all-ones keys, which rank after every real key and so stay in
+// the slots past the end.
+template <typename K, bool kVals, int kBlock, int kIpt>
+__global__ void __launch_bounds__(kBlock) lds_sort_kernel(LdsSortArgs a) {
+  constexpr int kWaves = kBlock / kWave;
+  constexpr int kTile = kBlock * kIpt;
+  constexpr int kWaveItems = kWave * kIpt;
+  constexpr int kScanThreads = kBlock < kRadix ? kBlock : kRadix;
+  constexpr int kDigitsPerThread = kRadix / kScanThreads;
+  constexpr int kScanWaves = kScanThreads / kWave;
+  constexpr size_t kDataBytes = kTile * (sizeof(K) > 4 ? sizeof(K) : 4);
+  __shared__ __attribute__((aligned(16))) unsigned char s_data[kDataBytes];
+  __shared__ uint32_t s_cnt[kWaves * kRadix];
+  __shared__ uint32_t s_wave_sum[kScanWaves];
+  K *s_keys = reinterpret_cast<K *>(s_data);
+  uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_data);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const K *__restrict__ kin = static_cast<const K *>(a.keys_in);
+  K *__restrict__ kout = static_cast<K *>(a.keys_out);
+  const uint32_t count = a.plan->count[a.cls];
+  const uint32_t *list = a.list;
+  const uint32_t wave_first = static_cast<uint32_t>(wave) * kWaveItems;
+
+  for (int x = tid; x < kWaves * kRadix; x += kBlock) s_cnt[x] = 0u;
+  __syncthreads();
+
+  for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
+    const uint32_t s = list[e];
+    const uint32_t lo = a.offsets[s];
+    const uint32_t len = a.offsets[s + 1] - lo;
+    K key[kIpt];
+    uint32_t val[kVals ? kIpt : 1];
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+      const uint32_t q = wave_first + i * kWave + lane;
+      key[i] = q < len ? kin[lo + q] : static_cast<K>(~static_cast<K>(0));
+      if constexpr (kVals) val[i] = q < len ? a.vals_in[lo + q] : 0u;
+    }
+    for (int j = 0; j < a.places; ++j) {
+      const int shift = a.begin_bit + j * kRadixBits;
+      const int width = min(kRadixBits, a.end_bit - shift);
+      const uint32_t mask = (1u << width) - 1u;
+      uint32_t pos[kIpt];
+#pragma unroll
+      for (int i = 0; i < kIpt; ++i) {
+        pos[i] = 0u;
+        if (wave_first + i * kWave < len) {
+          const uint32_t d = digit_of(key[i], shift, mask);
+          uint32_t peers_lo = ~0u, peers_hi = ~0u;
+#pragma unroll
+          for (int b = 0; b < kRadixBits; ++b) {
+            const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);
+            const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
+            peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
+            peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
+          }
+          uint32_t &c = s_cnt[wave * kRadix + d];
+          const uint32_t prior = c;
+          pos[i] = prior + __builtin_amdgcn_mbcnt_hi(peers_hi,
+                                                     __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+          c = prior + static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi));
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      __syncthreads();
+      // Digit starts: per digit an exclusive sum over waves, then over digits.
+      uint32_t excl[kDigitsPerThread];
+      uint32_t start = 0u;
+      if (tid < kScanThreads) {
+        uint32_t thread_total = 0u;
+#pragma unroll
+        for (int dd = 0; dd < kDigitsPerThread; ++dd) {
+          const int d = tid * kDigitsPerThread + dd;
+          uint32_t run = 0u;
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = s_cnt[w * kRadix + d];
+            s_cnt[w * kRadix + d] = run;
+            run += c;
+          }
+          excl[dd] = thread_total;
+          thread_total += run;
+        }
+        uint32_t incl = thread_total;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+          const uint32_t t = __shfl_up(incl, off, kWave);
+          if (lane >= off) incl += t;
+        }
+        if (kScanWaves > 1 && lane == kWave - 1) s_wave_sum[wave] = incl;
+        start = incl - thread_total;
+      }
+      if constexpr (kScanWaves > 1) __syncthreads();
+      if (tid < kScanThreads) {
+        if constexpr (kScanWaves > 1)
+          for (int w = 0; w < wave; ++w) start += s_wave_sum[w];
+#pragma unroll
+        for (int dd = 0; dd < kDigitsPerThread; ++dd) {
+          const int d = tid * kDigitsPerThread + dd;
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) s_cnt[w * kRadix + d] += start + excl[dd];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kIpt; ++i)
+        if (wave_first + i * kWave < len) {
+          pos[i] += s_cnt[wave * kRadix + digit_of(key[i], shift, mask)];
+          s_keys[pos[i]] = key[i];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kIpt; ++i)
+        if (wave_first + i * kWave < len) key[i] = s_keys[wave_first + i * kWave + lane];
+      if constexpr (kVals) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kIpt; ++i)
+          if (wave_first + i * kWave < len) s_vals[pos[i]] = val[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kIpt; ++i)
+          if (wave_first + i * kWave < len) val[i] = s_vals[wave_first + i * kWave + lane];
+      }
+      // The counters were last read before the scatter's barrier.
+      for (int x = tid; x < kWaves * kRadix; x += kBlock) s_cnt[x] = 0u;
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+      const uint32_t q = wave_first + i * kWave + lane;
+      if (q < len) {
+        kout[lo + q] = key[i];
+        if constexpr (kVals) a.vals_out[lo + q] = val[i];
+      }
+    }
+  }
+}
+
+// Classes: 64, 256 and 1024 threads, 8 keys per thread.
+constexpr int kLdsIpt = 8;
+constexpr int kLdsBlock[kSegClasses] = {64, 256, 1024};
+
+int lds_class_capacity(int cls) { return kLdsBlock[cls] * kLdsIpt; }
+
+int lds_class_block(int cls) { return kLdsBlock[cls]; }
+
+namespace {
+template <typename K, bool V, int B>
+const void *lds_kernel_ptr() {
+  return reinterpret_cast<const void *>(&lds_sort_kernel<K, V, B, kLdsIpt>);
+}
+
+const void *lds_kernel(int key_bits, bool has_values, int cls) {
+#define ONESWEEP_LDS_PICK(B)                                                             \
+  if (key_bits == 32)                                                                    \
+    return has_values ? lds_kernel_ptr<uint32_t, true, B>() : lds_kernel_ptr<uint32_t, false, B>(); \
+  return has_values ? lds_kernel_ptr<uint64_t, true, B>() : lds_kernel_ptr<uint64_t, false, B>();
+  switch (cls) {
+    case 0: {
+      ONESWEEP_LDS_PICK(64)
+    }
+    case 1: {
+      ONESWEEP_LDS_PICK(256)
+    }
+    default: {
+      ONESWEEP_LDS_PICK(1024)
+    }
+  }
+#undef ONESWEEP_LDS_PICK
+}
+}  // namespace
+
+hipError_t lds_sort_blocks_per_cu(int key_bits, bool has_values, int cls, int *blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, lds_kernel(key_bits, has_values, cls),
+                                                      kLdsBlock[cls], 0);
+}
+
+hipError_t launch_lds_sort(int key_bits, bool has_values, const LdsSortArgs &a, uint32_t grid,
+                           hipStream_t stream) {
+  const void *k = lds_kernel(key_bits, has_values, a.cls);
+  LdsSortArgs copy = a;
+  void *params[] = {&copy};
+  return hipLaunchKernel(k, dim3(grid), dim3(kLdsBlock[a.cls]), params, 0, stream);
+}
+
+}  // namespace onesweep

@@ -114,3 +114,42 @@ def test_empty_input_accepts_null_pointers():
                                   None) == 0
     assert lib.onesweep_sort_keys(ctypes.c_void_p(256), ctypes.byref(size), None, None, 0, 32, 0,
                                   32, 1, None, None) == 0
+
+
+def test_segmented_temp_query_and_validation():
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    n, S = 1 << 26, 20000
+    need = ow.sort_segments_temp_bytes(n, S, 32, True)
+    assert need >= 8 * n  # ping-pong keys and values for the large segments
+    # all segments fit in LDS: no temporary key buffer, no status rows
+    small_only = ow.sort_segments_temp_bytes(8192, 4, 32, True)
+    assert small_only < 8192
+    # every segment routed to the tile path needs more than the default
+    all_large = ow.make_config(segment_limits=(-1, -1, -1))
+    assert ow.sort_segments_temp_bytes(n, S, 32, True, config=all_large) > need
+    size = ctypes.c_size_t(0)
+    # keys without a segment
+    assert lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, None, None, 10, None,
+                                      0, 32, 0, 32, 1, None, None) == ow.ERROR_INVALID_VALUE
+    # too many segments
+    assert lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, None, None, 10, None,
+                                      1 << 30, 32, 0, 32, 1, None, None) == ow.ERROR_TOO_LARGE
+    # class limits beyond a class's capacity, or below -1
+    for limits in ((513, 0, 0), (0, 2049, 0), (0, 0, 8193), (-2, 0, 0)):
+        cfg = ow.make_config(segment_limits=limits)
+        assert lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, None, None, 10,
+                                          None, 1, 32, 0, 32, 1, ctypes.byref(cfg),
+                                          None) == ow.ERROR_INVALID_VALUE, limits
+    # a binning shape not built for the segmented path
+    cfg = ow.make_config(block_threads=512, items_per_thread=12)
+    assert lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, None, None, 10, None,
+                                      1, 32, 0, 32, 1, ctypes.byref(cfg),
+                                      None) == ow.ERROR_UNSUPPORTED
+    # NULL offsets with keys to sort
+    need = ow.sort_segments_temp_bytes(100, 1)
+    size = ctypes.c_size_t(need)
+    assert lib.onesweep_sort_segments(ctypes.c_void_p(1 << 20), ctypes.byref(size),
+                                      ctypes.c_void_p(4096), ctypes.c_void_p(8192), None, None,
+                                      100, None, 1, 32, 0, 32, 1, None,
+                                      None) == ow.ERROR_INVALID_VALUE
