@@ -39,6 +39,13 @@ WORKLOADS = {
     "u64_pairs_uniform": (64, True, "uniform", 27),
     "u32_keys_uniform_2p20": (32, False, "uniform", 20),
 }
+# Batched segmented workload: S segments with log-normal lengths (median 2000,
+# sigma 1.5, cap 2^22) scaled to 2^26 keys in total; uniform uint32 keys,
+# values = index within the segment.
+SEGMENT_WORKLOADS = {
+    # name: (segments, log2 total keys)
+    "segments_lognormal_20000": (20000, 26),
+}
 
 
 def log(*a):
@@ -170,12 +177,265 @@ def cpu_baseline(keys, vals, target_s=10.0):
                       f"median of {len(times)} single-threaded runs"}
 
 
+def segment_inputs(num_segments, log2n, seed=4):
+    import numpy as np
+    import workload as W
+    lengths = W.lognormal_segment_lengths(num_segments=num_segments, total=1 << log2n, seed=seed)
+    off = W.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    keys = W.uniform(seed, n)
+    seg_of = np.repeat(np.arange(num_segments), lengths)
+    vals = (np.arange(n, dtype=np.int64) - off[seg_of]).astype(np.uint32)
+    return lengths, off, keys, vals
+
+
+def cpu_baseline_segments(keys, vals, off, target_s=10.0):
+    """The CPU oracle on the first segments holding about 2^24 keys."""
+    import numpy as np
+    import oracle
+    last = int(np.searchsorted(off, 1 << 24, side="right")) - 1
+    last = max(last, 1)
+    cut = int(off[last])
+    o = off[: last + 1]
+    ks, vs = np.ascontiguousarray(keys[:cut]), np.ascontiguousarray(vals[:cut])
+    times = []
+    t_start = time.perf_counter()
+    while len(times) < 3 or (time.perf_counter() - t_start < target_s and len(times) < 10):
+        t0 = time.perf_counter()
+        oracle.sort_segments(ks, o, vs)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    return {"value": round(cut / med / 1e9, 4), "unit": "GKeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {last} segments ({cut} pairs) of the same input, median of "
+                      f"{len(times)} single-threaded runs"}
+
+
+def run_segments(args):
+    """Batched segmented sort under a captured graph, against per-segment
+    loops of the plain pair sort (eager, and captured in one graph)."""
+    import numpy as np
+    import torch
+    import paper_2206_01784_amd as ow
+
+    S, log2n = SEGMENT_WORKLOADS[args.workload]
+    log(f"[bench] workload={args.workload} generating input")
+    lengths, off, keys, vals = segment_inputs(S, log2n)
+    n = int(off[-1])
+    stream = torch.cuda.current_stream()
+    d_keys = torch.from_numpy(keys).cuda()
+    d_vals = torch.from_numpy(vals).cuda()
+    d_off = torch.from_numpy(off.astype(np.uint32)).cuda()
+    d_kout = torch.empty_like(d_keys)
+    d_vout = torch.empty_like(d_vals)
+    cfg = ow.make_config(args.block, args.ipt, rank_algorithm=args.rank,
+                         segment_limits=tuple(args.segment_limits))
+    temp = torch.empty(ow.sort_segments_temp_bytes(n, S, 32, True, config=cfg),
+                       dtype=torch.uint8, device="cuda")
+
+    def batched(cfg_, s=stream):
+        ow.sort_segments(d_keys, d_off, d_vals, keys_out=d_kout, values_out=d_vout, temp=temp,
+                         config=cfg_, stream=s)
+
+    for _ in range(max(args.warmup, 1)):
+        batched(cfg)
+    torch.cuda.synchronize()
+    # Per-kernel durations from eager traced runs (events around each launch).
+    launches = 16
+    per_kind = {}
+    for _ in range(3):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * launches)]
+        for e in evs:
+            e.record(stream)
+        arr = (ctypes.c_void_p * len(evs))(*[e.cuda_event for e in evs])
+        tr = ow.Trace()
+        tr.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+        tr.capacity = launches
+        cfg_t = ow.make_config(args.block, args.ipt, rank_algorithm=args.rank,
+                               segment_limits=tuple(args.segment_limits), trace=tr)
+        batched(cfg_t)
+        torch.cuda.synchronize()
+        for i in range(tr.count):
+            per_kind.setdefault((i, tr.kinds[i]), []).append(evs[2 * i].elapsed_time(evs[2 * i + 1]))
+    for (i, kind), ts in sorted(per_kind.items()):
+        log(f"[bench]   launch {i:2d} {ow.KERNEL_NAMES[kind]:9s} avg={statistics.mean(ts) * 1e3:9.2f} us")
+
+    # Timed: replays of one captured graph of the whole batched sort.
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g, stream=cap):
+            batched(cfg, cap)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        g.replay()
+    end.record()
+    torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(end) / args.steps
+    value = n / (ms_per_step * 1e-3) / 1e9
+    log(f"[bench] batched graph: {ms_per_step:.3f} ms per sort, {value:.2f} GKeys/s")
+    if int(temp[:4].cpu().numpy().view(np.uint32)[0]) != 0:
+        log("[bench] ERROR: offsets reported invalid")
+        sys.exit(1)
+    # spot check: a few segments against the oracle
+    import oracle
+    out_k, out_v = d_kout.cpu().numpy(), d_vout.cpu().numpy()
+    for s_ in (0, S // 2, int(np.argmax(lengths)), S - 1):
+        a, b = int(off[s_]), int(off[s_ + 1])
+        wk, wv = oracle.sort_segments(keys[a:b], np.array([0, b - a]), vals[a:b])
+        if not (np.array_equal(out_k[a:b], wk) and np.array_equal(out_v[a:b], wv)):
+            log(f"[bench] ERROR: segment {s_} differs from the oracle")
+            sys.exit(1)
+
+    # Baseline 1: a loop of plain pair sorts, one per segment, eager.
+    seg_temp = torch.empty(ow.sort_temp_bytes(int(lengths.max()), 32, True), dtype=torch.uint8,
+                           device="cuda")
+    bounds = [(int(off[i]), int(off[i + 1])) for i in range(S) if off[i + 1] > off[i]]
+
+    def loop(s=stream):
+        for a, b in bounds:
+            ow.sort_pairs(d_keys[a:b], d_vals[a:b], keys_out=d_kout[a:b], values_out=d_vout[a:b],
+                          temp=seg_temp, stream=s)
+
+    loop()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    loop()
+    end.record()
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3
+    loop_gpu_ms = start.elapsed_time(end)
+    log(f"[bench] per-segment loop (eager): {loop_ms:.1f} ms wall, {loop_gpu_ms:.1f} ms on the stream")
+    # Baseline 2: the same loop captured once into a graph.
+    g2 = torch.cuda.CUDAGraph()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g2, stream=cap):
+            loop(cap)
+    torch.cuda.synchronize()
+    cap_s = time.perf_counter() - t0
+    g2.replay()
+    torch.cuda.synchronize()
+    start.record()
+    g2.replay()
+    end.record()
+    torch.cuda.synchronize()
+    loop_graph_ms = start.elapsed_time(end)
+    log(f"[bench] per-segment loop (graph, captured in {cap_s:.1f} s): {loop_graph_ms:.1f} ms")
+    del g2
+
+    bins = per_kind_summary(per_kind, ow, lengths, args.segment_limits)
+    dom_kind, dom_us, dom_launches = bins["dominant"]
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GKeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched stable sort of {S} segments (log-normal lengths, median 2000, "
+                        f"sigma 1.5, scaled to 2^{log2n} uint32 key/value pairs), one graph replay",
+            "n": n, "segments": S, "key_bits": 32, "values": True,
+            "segment_limits": list(args.segment_limits),
+            "tile": ow.tile_items(32, True, cfg),
+        },
+        "baselines": {
+            "per_segment_loop_ms": round(loop_gpu_ms, 2),
+            "per_segment_loop_wall_ms": round(loop_ms, 2),
+            "per_segment_loop_graph_ms": round(loop_graph_ms, 2),
+            "speedup_vs_loop": round(loop_gpu_ms / ms_per_step, 1),
+            "speedup_vs_loop_graph": round(loop_graph_ms / ms_per_step, 1),
+        },
+        "kernels_us": bins["table"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    if dom_kind is not None:
+        result["roofline"] = bins["roofline"]
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline_segments(keys, vals, off)
+    print(json.dumps(result), flush=True)
+
+
+SEGMENT_CLASS_CAPACITY = (512, 2048, 8192)
+
+
+def segment_class_keys(lengths, limits):
+    """Keys per LDS class and in large segments, with the library's rule:
+    class c takes lengths in (limit[c-1], limit[c]]; -1 = class unused,
+    0 = the class's capacity."""
+    import numpy as np
+    eff, prev = [], 0
+    for c, v in enumerate(limits):
+        if v != -1:
+            prev = max(prev, SEGMENT_CLASS_CAPACITY[c] if v == 0 else v)
+        eff.append(prev)
+    lengths = np.asarray(lengths)
+    keys, lo = [], 0
+    for hi in eff:
+        keys.append(int(lengths[(lengths > lo) & (lengths <= hi)].sum()) if hi > lo else 0)
+        lo = hi
+    large = int(lengths[lengths > lo].sum())
+    return keys, large
+
+
+def per_kind_summary(per_kind, ow, lengths, limits, pair_bytes=8):
+    """Average duration of every launch of the batched sort, and the roofline
+    of the kernel kind that takes the most time per sort. Algorithmic bytes
+    of a launch: one read and one write of every key and value it moves (LDS
+    sort: the keys of its class; binning: the keys of the large segments)."""
+    table, totals = {}, {}
+    class_keys, large_keys = segment_class_keys(lengths, limits)
+    lds_index = 0
+    for (i, kind), ts in sorted(per_kind.items()):
+        us = statistics.mean(ts) * 1e3
+        table[f"{i}:{ow.KERNEL_NAMES[kind]}"] = round(us, 2)
+        if kind == ow.KERNEL_LDS_SORT:
+            moved = class_keys[lds_index] if lds_index < 3 else 0
+            lds_index += 1
+        elif kind == ow.KERNEL_BINNING:
+            moved = large_keys
+        else:
+            continue
+        t = totals.setdefault(kind, [0.0, 0, 0])
+        t[0] += us
+        t[1] += 1
+        t[2] += 2 * pair_bytes * moved
+    if not totals:
+        return {"table": table, "dominant": (None, 0.0, 0), "roofline": None}
+    kind = max(totals, key=lambda k: totals[k][0])
+    us, launches, nbytes = totals[kind]
+    per_launch_bytes = nbytes / launches
+    avg_us = us / launches
+    achieved = per_launch_bytes / (avg_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": ow.KERNEL_NAMES[kind], "algorithmic_bytes_per_launch": int(per_launch_bytes),
+            "avg_launch_us": round(avg_us, 2)}
+    return {"table": table, "dominant": (kind, avg_us, launches), "roofline": roof}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="u32_keys_uniform", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="u32_keys_uniform",
+                    choices=sorted(WORKLOADS) + sorted(SEGMENT_WORKLOADS))
+    ap.add_argument("--segment-limits", type=int, nargs=3, default=(0, 0, 0))
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--hist-blocks-per-cu", type=int, default=0)
@@ -204,6 +464,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload in SEGMENT_WORKLOADS:
+        run_segments(args)
+        return
     key_bits, has_vals, dist, log2n = WORKLOADS[args.workload]
     n = 1 << log2n
     log(f"[bench] workload={args.workload} n=2^{log2n} generating input")

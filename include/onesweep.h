@@ -194,6 +194,26 @@ onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
                                          int end_bit, int stable, const onesweep_config_t *cfg,
                                          onesweep_stream_t stream);
 
+/*
+ * Autotuner of the segmented sort (not in the paper): times
+ * onesweep_sort_segments on the caller's data for every built tile shape of
+ * the segmented path crossed with a fixed set of segment class limits
+ * (`repetitions` timed runs each, after one warm-up), writes the fastest
+ * configuration to *cfg_out and leaves the output sorted by it. Arguments as
+ * in onesweep_sort_segments, except that input and output must not alias
+ * (the input is sorted many times). Temp storage: the largest any candidate
+ * needs (size query with d_temp == NULL). Unlike the sort, this call creates
+ * two HIP events and synchronises on them; it is not graph-capturable.
+ * cfg_out->trace is NULL on return.
+ */
+onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
+                                         const void *d_keys_in, void *d_keys_out,
+                                         const uint32_t *d_vals_in, uint32_t *d_vals_out,
+                                         size_t n, const uint32_t *d_seg_offsets,
+                                         size_t num_segments, int key_bits, int begin_bit,
+                                         int end_bit, int repetitions,
+                                         onesweep_config_t *cfg_out, onesweep_stream_t stream);
+
 /* Binning tile size T = block_threads x items_per_thread that `cfg` resolves
  * to for this key width and value presence; 0 if the config is unsupported.
  * Pure host computation. */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libonesweep.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first "
-        "(python -m paper_2206_01784_amd.build, or __graft_entry__.build())")
+        "(python paper_2206_01784_amd/build.py, or __graft_entry__.build())")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -62,6 +62,9 @@ _lib.onesweep_binning_pass.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _i32,
                                        _cfgp, _vp]
 _lib.onesweep_sort_segments.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _i32, _i32,
                                         _i32, _i32, _cfgp, _vp]
+_lib.onesweep_tune_segments.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _i32, _i32,
+                                        _i32, _i32, _cfgp, _vp]
+_lib.onesweep_tune_segments.restype = _i32
 _lib.onesweep_tile_items.argtypes = [_i32, _i32, _cfgp]
 _lib.onesweep_tile_items.restype = _sz
 _lib.onesweep_last_error.restype = ctypes.c_char_p
@@ -301,3 +304,34 @@ def sort_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tenso
                                        kb, begin_bit, end_bit, 1, _cfg_ptr(config),
                                        _stream(stream)))
     return (keys_out, values_out) if has_values else keys_out
+
+
+def tune_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tensor | None = None,
+                  begin_bit: int = 0, end_bit: int | None = None,
+                  keys_out: torch.Tensor | None = None, values_out: torch.Tensor | None = None,
+                  repetitions: int = 3, stream=None) -> Config:
+    """Time the segmented sort's candidate configurations on this data and
+    return the fastest (the outputs hold the sorted segments afterwards)."""
+    kb = _key_bits(keys)
+    end_bit = kb if end_bit is None else end_bit
+    n = keys.numel()
+    num_segments = offsets.numel() - 1
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    if values is not None and values_out is None:
+        values_out = torch.empty_like(values)
+    size = ctypes.c_size_t(0)
+    dummy = ctypes.c_void_p(4) if values is not None else None
+    _check(_lib.onesweep_tune_segments(None, ctypes.byref(size), None, None, dummy, dummy, n, None,
+                                       num_segments, kb, begin_bit, end_bit, repetitions, None,
+                                       None))
+    cfg = Config()
+    _check(_lib.onesweep_tune_segments(None, ctypes.byref(size), None, None, dummy, dummy, n, None,
+                                       num_segments, kb, begin_bit, end_bit, repetitions,
+                                       ctypes.byref(cfg), None))
+    temp = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=keys.device)
+    size = ctypes.c_size_t(temp.numel())
+    _check(_lib.onesweep_tune_segments(_dev_ptr(temp), ctypes.byref(size), _dev_ptr(keys),
+                                       _dev_ptr(keys_out), _dev_ptr(values), _dev_ptr(values_out),
+                                       n, _dev_ptr(offsets), num_segments, kb, begin_bit, end_bit,
+                                       repetitions, ctypes.byref(cfg), _stream(stream)))
+    return cfg

@@ -4,7 +4,9 @@ Every HIP translation unit under csrc/ is compiled with hipcc for gfx950 only
 and linked into one shared library next to this file. Packed-FP32
 instructions are disabled for all device code.
 
-    python -m paper_2206_01784_amd.build
+    python paper_2206_01784_amd/build.py
+
+(Run by path: importing the package would load the library being rebuilt.)
 """
 from __future__ import annotations
 

@@ -784,6 +784,105 @@ onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
                        cfg, reinterpret_cast<hipStream_t>(stream));
 }
 
+onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
+                                         const void *d_keys_in, void *d_keys_out,
+                                         const uint32_t *d_vals_in, uint32_t *d_vals_out,
+                                         size_t n, const uint32_t *d_seg_offsets,
+                                         size_t num_segments, int key_bits, int begin_bit,
+                                         int end_bit, int repetitions,
+                                         onesweep_config_t *cfg_out, onesweep_stream_t stream) {
+  // Candidates: every tile shape built for the segmented path, crossed with
+  // class limits that move segments between the LDS classes and the tile
+  // path.
+  static const int kShapes32[][2] = {{256, 16}, {512, 16}, {1024, 8}};
+  static const int kShapes64[][2] = {{256, 16}, {512, 8}, {1024, 8}};
+  static const int kLimits[][3] = {{0, 0, 0},   {0, 0, 4096},  {0, 0, 2048}, {0, 0, -1},
+                                   {0, -1, 0},  {-1, 0, 0},    {256, 1024, 4096}};
+  constexpr int kNumShapes = 3, kNumLimits = sizeof(kLimits) / sizeof(kLimits[0]);
+  auto candidate = [&](int i) {
+    onesweep_config_t c{};
+    const int(*shapes)[2] = key_bits == 64 ? kShapes64 : kShapes32;
+    c.block_threads = shapes[i / kNumLimits][0];
+    c.items_per_thread = shapes[i / kNumLimits][1];
+    for (int k = 0; k < 3; ++k) c.segment_limits[k] = kLimits[i % kNumLimits][k];
+    return c;
+  };
+  const int count = kNumShapes * kNumLimits;
+  g_error[0] = '\0';
+  if (temp_bytes == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp_bytes is NULL");
+  if (cfg_out == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "cfg_out is NULL");
+  if (d_keys_in != nullptr && d_keys_in == d_keys_out)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "the tuner needs separate input and output");
+  if (d_vals_in != nullptr && d_vals_in == d_vals_out)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "the tuner needs separate input and output");
+  if (repetitions < 1 || repetitions > 100)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "repetitions %d not in [1, 100]", repetitions);
+  size_t need = 0;
+  for (int i = 0; i < count; ++i) {
+    onesweep_config_t c = candidate(i);
+    size_t sz = 0;
+    onesweep_status_t st = onesweep_sort_segments(nullptr, &sz, d_keys_in, d_keys_out, d_vals_in,
+                                                  d_vals_out, n, d_seg_offsets, num_segments,
+                                                  key_bits, begin_bit, end_bit, 1, &c, stream);
+    if (st) return st;
+    need = std::max(need, sz);
+  }
+  if (d_temp == nullptr) {
+    *temp_bytes = need;
+    return ONESWEEP_SUCCESS;
+  }
+  if (*temp_bytes < need)
+    return fail(ONESWEEP_ERROR_INSUFFICIENT_TEMP, "temp storage %zu bytes, need %zu",
+                *temp_bytes, need);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return hip_fail(e, "hipEventCreate");
+  }
+  onesweep_status_t st = ONESWEEP_SUCCESS;
+  float best_ms = 0.0f;
+  int best = -1;
+  for (int i = 0; i < count && st == ONESWEEP_SUCCESS; ++i) {
+    onesweep_config_t c = candidate(i);
+    size_t sz = *temp_bytes;
+    auto run = [&]() {
+      return onesweep_sort_segments(d_temp, &sz, d_keys_in, d_keys_out, d_vals_in, d_vals_out, n,
+                                    d_seg_offsets, num_segments, key_bits, begin_bit, end_bit, 1,
+                                    &c, stream);
+    };
+    if ((st = run())) break;  // warm-up
+    if ((e = hipEventRecord(ev[0], s)) != hipSuccess) { st = hip_fail(e, "hipEventRecord"); break; }
+    for (int r = 0; r < repetitions && st == ONESWEEP_SUCCESS; ++r) st = run();
+    if (st) break;
+    if ((e = hipEventRecord(ev[1], s)) != hipSuccess ||
+        (e = hipEventSynchronize(ev[1])) != hipSuccess) {
+      st = hip_fail(e, "timing event");
+      break;
+    }
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) {
+      st = hip_fail(e, "hipEventElapsedTime");
+      break;
+    }
+    if (best < 0 || ms < best_ms) {
+      best = i;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (st) return st;
+  *cfg_out = candidate(best);
+  // Leave the output sorted by the chosen configuration.
+  size_t sz = *temp_bytes;
+  return onesweep_sort_segments(d_temp, &sz, d_keys_in, d_keys_out, d_vals_in, d_vals_out, n,
+                                d_seg_offsets, num_segments, key_bits, begin_bit, end_bit, 1,
+                                cfg_out, stream);
+}
+
 size_t onesweep_tile_items(int key_bits, int has_values, const onesweep_config_t *cfg) {
   if (key_bits != 32 && key_bits != 64) return 0;
   Resolved rc;

@@ -254,3 +254,23 @@ def test_segments_graph_capture_replays(ow):
         eager = ow.sort_segments(dev(keys), dev(off.astype(np.uint32)))
         torch.cuda.synchronize()
         assert np.array_equal(host(eager), want_k), seed
+
+
+def test_segments_tuner_picks_a_built_config_and_sorts(ow):
+    lengths = W.lognormal_segment_lengths(num_segments=1000, total=1 << 21, seed=22)
+    off = W.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    keys = W.uniform(22, n)
+    vals = np.arange(n, dtype=np.uint32)
+    tk, tv, to = dev(keys), dev(vals), dev(off.astype(np.uint32))
+    ko, vo = torch.empty_like(tk), torch.empty_like(tv)
+    cfg = ow.tune_segments(tk, to, tv, keys_out=ko, values_out=vo, repetitions=2)
+    torch.cuda.synchronize()
+    want_k, want_v = oracle.sort_segments(keys, off, vals)
+    assert np.array_equal(host(ko), want_k)
+    assert np.array_equal(host(vo), want_v)
+    assert (cfg.block_threads, cfg.items_per_thread) in [(256, 16), (512, 16), (1024, 8)]
+    # the chosen config sorts the same data bit-exactly again
+    k2, v2 = ow.sort_segments(tk, to, tv, config=cfg)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(k2), want_k) and np.array_equal(host(v2), want_v)
