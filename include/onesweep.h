@@ -204,7 +204,7 @@ onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
  * (the input is sorted many times). Temp storage: the largest any candidate
  * needs (size query with d_temp == NULL). Unlike the sort, this call creates
  * two HIP events and synchronises on them; it is not graph-capturable.
- * cfg_out->trace is NULL on return.
+ * cfg_out->trace is NULL on return; cfg_out may be NULL for the size query.
  */
 onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
                                          const void *d_keys_in, void *d_keys_out,
@@ -213,6 +213,101 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
                                          size_t num_segments, int key_bits, int begin_bit,
                                          int end_bit, int repetitions,
                                          onesweep_config_t *cfg_out, onesweep_stream_t stream);
+
+/*
+ * ---- Learned configuration selection (not in the paper; the paper's
+ * kernels are tuned by hand, Table 2). A small MLP predicts, from features
+ * of a key sample, each configuration's sort time relative to the fastest,
+ * and the selector picks the smallest prediction. The choice never changes
+ * the sort's output (every configuration produces the unique stable order);
+ * it changes the binning tile shape and the ranking method.
+ *
+ * Features (ONESWEEP_FEATURES floats): for each of the 8 digit places
+ * (Section 1's p places of 8 bits over [begin_bit, end_bit); places past p
+ * are zero) a 256-bin histogram of min(n, 4096) keys sampled at indices
+ * floor(i * n / m), as fractions of the sample; then log2(n) / 32,
+ * key_bits / 64 and has_values.
+ *
+ * Network (float32, ONESWEEP_MODEL_PARAMS parameters in one flat array):
+ * a place encoder shared by the 8 places (256 -> 16, ReLU), the 8 encodings
+ * and 3 scalars concatenated (131) -> 64 ReLU -> 64 ReLU -> 12 outputs.
+ * Layout: We[256][16], be[16], W1[131][64], b1[64], W2[64][64], b2[64],
+ * W3[64][12], b3[12], row-major with the input index first.
+ *
+ * Training: masked mean squared error between the outputs and targets
+ * log(time_c / fastest time) of the configurations c that apply (mask 1),
+ * then Adam (Kingma and Ba, arXiv 1412.6980; beta1 0.9, beta2 0.999,
+ * eps 1e-8). Training batches pass the histogram part (batch x 2048, row
+ * b = features[0:2048] of input b) and the scalar part (batch x 3)
+ * separately.
+ *
+ * Model objects own device memory (allocated by create/load on the current
+ * device, freed by onesweep_model_free); these calls may allocate and
+ * synchronise and are not for graph capture, except onesweep_features and
+ * onesweep_model_infer, which enqueue one kernel each.
+ */
+#define ONESWEEP_FEATURES 2051
+#define ONESWEEP_MODEL_CLASSES 12
+#define ONESWEEP_MODEL_PARAMS 17500
+
+typedef struct onesweep_model onesweep_model_t;
+
+/* New model: zero parameters, the default class table (every tile shape of
+ * the plain sort with both ranking methods). max_batch bounds the training
+ * batch (1..65536). */
+onesweep_status_t onesweep_model_create(int max_batch, onesweep_model_t **model);
+/* Model from a file written by onesweep_model_save (parameters and class
+ * table); Adam state starts at zero. */
+onesweep_status_t onesweep_model_load(const char *path, int max_batch, onesweep_model_t **model);
+onesweep_status_t onesweep_model_save(const onesweep_model_t *model, const char *path);
+void onesweep_model_free(onesweep_model_t *model);
+size_t onesweep_model_num_params(void);
+/* Host <-> device copies of the flat parameters (count must equal
+ * ONESWEEP_MODEL_PARAMS); set also resets the Adam state and step. */
+onesweep_status_t onesweep_model_set_params(onesweep_model_t *model, const float *host_params,
+                                            size_t count);
+onesweep_status_t onesweep_model_get_params(const onesweep_model_t *model, float *host_params,
+                                            size_t count);
+/* Configuration of class `index` (0..11) and its key-width mask (bit 0:
+ * 32-bit keys, bit 1: 64-bit keys). */
+onesweep_status_t onesweep_model_class(const onesweep_model_t *model, int index,
+                                       onesweep_config_t *cfg_out, int *key_bits_mask);
+
+/* Features of n device keys into d_features (ONESWEEP_FEATURES floats,
+ * device). One kernel. */
+onesweep_status_t onesweep_features(const void *d_keys, size_t n, int key_bits, int begin_bit,
+                                    int end_bit, int has_values, float *d_features,
+                                    onesweep_stream_t stream);
+/* One forward pass (one kernel): d_out[12] predictions, *d_choice = the
+ * class with the smallest prediction among the set bits of class_mask
+ * (-1 if none). */
+onesweep_status_t onesweep_model_infer(const onesweep_model_t *model, const float *d_features,
+                                       unsigned class_mask, float *d_out, int *d_choice,
+                                       onesweep_stream_t stream);
+/* Batched forward (the training path): d_out[batch][12]. */
+onesweep_status_t onesweep_model_forward(onesweep_model_t *model, const float *d_hist,
+                                         const float *d_scalars, int batch, float *d_out,
+                                         onesweep_stream_t stream);
+/* Loss (d_loss, 1 float, may be NULL) and its gradient with respect to
+ * every parameter (d_grad, ONESWEEP_MODEL_PARAMS floats, parameter layout).
+ * d_y and d_mask: batch x 12. */
+onesweep_status_t onesweep_model_gradients(onesweep_model_t *model, const float *d_hist,
+                                           const float *d_scalars, const float *d_y,
+                                           const float *d_mask, int batch, float *d_grad,
+                                           float *d_loss, onesweep_stream_t stream);
+/* gradients, then one Adam step with learning rate lr. */
+onesweep_status_t onesweep_model_train_step(onesweep_model_t *model, const float *d_hist,
+                                            const float *d_scalars, const float *d_y,
+                                            const float *d_mask, int batch, float lr,
+                                            float *d_loss, onesweep_stream_t stream);
+/* Configuration for sorting these keys: features, one forward pass and the
+ * best class that applies to key_bits, then a synchronisation of `stream`
+ * to read the choice. A NULL model (or n == 0) yields the library default
+ * (all fields 0). cfg_out->trace is NULL. */
+onesweep_status_t onesweep_select_config(const onesweep_model_t *model, const void *d_keys,
+                                         size_t n, int key_bits, int begin_bit, int end_bit,
+                                         int has_values, onesweep_config_t *cfg_out,
+                                         onesweep_stream_t stream);
 
 /* Binning tile size T = block_threads x items_per_thread that `cfg` resolves
  * to for this key width and value presence; 0 if the config is unsupported.

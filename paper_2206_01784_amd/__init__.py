@@ -325,13 +325,153 @@ def tune_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tenso
                                        num_segments, kb, begin_bit, end_bit, repetitions, None,
                                        None))
     cfg = Config()
-    _check(_lib.onesweep_tune_segments(None, ctypes.byref(size), None, None, dummy, dummy, n, None,
-                                       num_segments, kb, begin_bit, end_bit, repetitions,
-                                       ctypes.byref(cfg), None))
     temp = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=keys.device)
     size = ctypes.c_size_t(temp.numel())
     _check(_lib.onesweep_tune_segments(_dev_ptr(temp), ctypes.byref(size), _dev_ptr(keys),
                                        _dev_ptr(keys_out), _dev_ptr(values), _dev_ptr(values_out),
                                        n, _dev_ptr(offsets), num_segments, kb, begin_bit, end_bit,
                                        repetitions, ctypes.byref(cfg), _stream(stream)))
+    return cfg
+
+
+# ------------------------------------------------------------------ learned configuration
+FEATURES = 2051
+MODEL_CLASSES = 12
+MODEL_PARAMS = 17500
+_fp = ctypes.POINTER(ctypes.c_float)
+_lib.onesweep_model_create.argtypes = [_i32, ctypes.POINTER(_vp)]
+_lib.onesweep_model_load.argtypes = [ctypes.c_char_p, _i32, ctypes.POINTER(_vp)]
+_lib.onesweep_model_save.argtypes = [_vp, ctypes.c_char_p]
+_lib.onesweep_model_free.argtypes = [_vp]
+_lib.onesweep_model_free.restype = None
+_lib.onesweep_model_num_params.restype = _sz
+_lib.onesweep_model_set_params.argtypes = [_vp, _vp, _sz]
+_lib.onesweep_model_get_params.argtypes = [_vp, _vp, _sz]
+_lib.onesweep_model_class.argtypes = [_vp, _i32, _cfgp, ctypes.POINTER(_i32)]
+_lib.onesweep_features.argtypes = [_vp, _sz, _i32, _i32, _i32, _i32, _vp, _vp]
+_lib.onesweep_model_infer.argtypes = [_vp, _vp, ctypes.c_uint, _vp, _vp, _vp]
+_lib.onesweep_model_forward.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp]
+_lib.onesweep_model_gradients.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]
+_lib.onesweep_model_train_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, _vp,
+                                           _vp]
+_lib.onesweep_select_config.argtypes = [_vp, _vp, _sz, _i32, _i32, _i32, _i32, _cfgp, _vp]
+for _f in ("onesweep_model_create", "onesweep_model_load", "onesweep_model_save",
+           "onesweep_model_set_params", "onesweep_model_get_params", "onesweep_model_class",
+           "onesweep_features", "onesweep_model_infer", "onesweep_model_forward",
+           "onesweep_model_gradients", "onesweep_model_train_step", "onesweep_select_config"):
+    getattr(_lib, _f).restype = _i32
+
+
+def features(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
+             has_values: bool = False, out: torch.Tensor | None = None, stream=None):
+    """Sampled digit-histogram features of the keys (float32, FEATURES values)."""
+    kb = _key_bits(keys)
+    end_bit = kb if end_bit is None else end_bit
+    if out is None:
+        out = torch.empty(FEATURES, dtype=torch.float32, device=keys.device)
+    _check(_lib.onesweep_features(_dev_ptr(keys), keys.numel(), kb, begin_bit, end_bit,
+                                  int(has_values), _dev_ptr(out), _stream(stream)))
+    return out
+
+
+class Model:
+    """A configuration-selection MLP on the current GPU (owns device memory)."""
+
+    def __init__(self, max_batch: int = 1024, path: str | None = None):
+        self._h = ctypes.c_void_p()
+        if path is None:
+            _check(_lib.onesweep_model_create(max_batch, ctypes.byref(self._h)))
+        else:
+            _check(_lib.onesweep_model_load(os.fsencode(path), max_batch, ctypes.byref(self._h)))
+        self.max_batch = max_batch
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.onesweep_model_free(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def save(self, path: str):
+        _check(_lib.onesweep_model_save(self._h, os.fsencode(path)))
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != MODEL_PARAMS:
+            raise ValueError(f"expected {MODEL_PARAMS} parameters")
+        _check(_lib.onesweep_model_set_params(self._h, a.ctypes.data, a.size))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(MODEL_PARAMS, dtype=np.float32)
+        _check(_lib.onesweep_model_get_params(self._h, a.ctypes.data, a.size))
+        return a
+
+    def class_config(self, index: int):
+        """(Config, key_bits_mask) of one class."""
+        cfg = Config()
+        mask = ctypes.c_int(0)
+        _check(_lib.onesweep_model_class(self._h, index, ctypes.byref(cfg), ctypes.byref(mask)))
+        return cfg, mask.value
+
+    def infer(self, feats: torch.Tensor, class_mask: int = (1 << MODEL_CLASSES) - 1,
+              stream=None):
+        out = torch.empty(MODEL_CLASSES, dtype=torch.float32, device=feats.device)
+        choice = torch.empty(1, dtype=torch.int32, device=feats.device)
+        _check(_lib.onesweep_model_infer(self._h, _dev_ptr(feats), class_mask, _dev_ptr(out),
+                                         _dev_ptr(choice), _stream(stream)))
+        return out, choice
+
+    @staticmethod
+    def _split(x: torch.Tensor):
+        if x.dim() != 2 or x.shape[1] != FEATURES or x.dtype != torch.float32:
+            raise ValueError("x must be float32 of shape (batch, FEATURES)")
+        return x[:, : FEATURES - 3].contiguous(), x[:, FEATURES - 3:].contiguous()
+
+    def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        hist, scal = self._split(x)
+        out = torch.empty((x.shape[0], MODEL_CLASSES), dtype=torch.float32, device=x.device)
+        _check(_lib.onesweep_model_forward(self._h, _dev_ptr(hist), _dev_ptr(scal), x.shape[0],
+                                           _dev_ptr(out), _stream(stream)))
+        return out
+
+    def gradients(self, x: torch.Tensor, y: torch.Tensor, mask: torch.Tensor, stream=None):
+        """(loss, flat gradient) of the masked squared error."""
+        hist, scal = self._split(x)
+        grad = torch.empty(MODEL_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(_lib.onesweep_model_gradients(self._h, _dev_ptr(hist), _dev_ptr(scal),
+                                             _dev_ptr(y.contiguous()),
+                                             _dev_ptr(mask.contiguous()), x.shape[0],
+                                             _dev_ptr(grad), _dev_ptr(loss), _stream(stream)))
+        return loss, grad
+
+    def train_step(self, x: torch.Tensor, y: torch.Tensor, mask: torch.Tensor, lr: float = 1e-3,
+                   stream=None, split=None):
+        """One Adam step on a batch; returns the loss tensor (before the step)."""
+        hist, scal = self._split(x) if split is None else split
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(_lib.onesweep_model_train_step(self._h, _dev_ptr(hist), _dev_ptr(scal),
+                                              _dev_ptr(y), _dev_ptr(mask), x.shape[0], lr,
+                                              _dev_ptr(loss), _stream(stream)))
+        return loss
+
+    def select_config(self, keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
+                      has_values: bool = False, stream=None) -> Config:
+        return select_config(self, keys, begin_bit, end_bit, has_values, stream)
+
+
+def select_config(model: Model | None, keys: torch.Tensor, begin_bit: int = 0,
+                  end_bit: int | None = None, has_values: bool = False, stream=None) -> Config:
+    """Configuration the model picks for these keys (synchronises the stream)."""
+    kb = _key_bits(keys)
+    end_bit = kb if end_bit is None else end_bit
+    cfg = Config()
+    _check(_lib.onesweep_select_config(None if model is None else model.handle, _dev_ptr(keys),
+                                       keys.numel(), kb, begin_bit, end_bit, int(has_values),
+                                       ctypes.byref(cfg), _stream(stream)))
     return cfg

@@ -10,11 +10,9 @@
 #include <algorithm>
 #include <atomic>
 
-#include "../../include/onesweep.h"
 #include "internal.hpp"
 
 namespace onesweep {
-namespace {
 
 thread_local char g_error[512] = "";
 
@@ -29,6 +27,10 @@ onesweep_status_t fail(onesweep_status_t code, const char *fmt, ...) {
 onesweep_status_t hip_fail(hipError_t e, const char *what) {
   return fail(ONESWEEP_ERROR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+void clear_error() { g_error[0] = '\0'; }
+
+namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxN = size_t(1) << 30;  // 30-bit status values
@@ -810,10 +812,10 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
   const int count = kNumShapes * kNumLimits;
   g_error[0] = '\0';
   if (temp_bytes == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp_bytes is NULL");
-  if (cfg_out == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "cfg_out is NULL");
-  if (d_keys_in != nullptr && d_keys_in == d_keys_out)
-    return fail(ONESWEEP_ERROR_INVALID_VALUE, "the tuner needs separate input and output");
-  if (d_vals_in != nullptr && d_vals_in == d_vals_out)
+  if (d_temp != nullptr && cfg_out == nullptr)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "cfg_out is NULL");
+  if (d_temp != nullptr && ((d_keys_in != nullptr && d_keys_in == d_keys_out) ||
+                            (d_vals_in != nullptr && d_vals_in == d_vals_out)))
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "the tuner needs separate input and output");
   if (repetitions < 1 || repetitions > 100)
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "repetitions %d not in [1, 100]", repetitions);

@@ -324,6 +324,14 @@ __global__ void __launch_bounds__(kBlock)
 // Instantiated shapes: (key type, values, workgroup size, items per thread,
 // rank algorithm).
 #define ONESWEEP_BINNING_SHAPES(X)    \
+  X(uint32_t, false, 256, 8, 0)       \
+  X(uint32_t, false, 256, 8, 1)       \
+  X(uint32_t, true, 256, 8, 0)        \
+  X(uint32_t, true, 256, 8, 1)        \
+  X(uint64_t, false, 256, 8, 0)       \
+  X(uint64_t, false, 256, 8, 1)       \
+  X(uint64_t, true, 256, 8, 0)        \
+  X(uint64_t, true, 256, 8, 1)        \
   X(uint32_t, false, 256, 16, 0)      \
   X(uint32_t, false, 512, 16, 0)      \
   X(uint32_t, false, 512, 12, 0)      \

@@ -7,9 +7,15 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/onesweep.h"
 #include "device_common.hpp"
 
 namespace onesweep {
+
+// Thread-local error message of the C ABI (api.hip).
+onesweep_status_t fail(onesweep_status_t code, const char *fmt, ...);
+onesweep_status_t hip_fail(hipError_t e, const char *what);
+void clear_error();
 
 // One binning-kernel instantiation: key width, values or not, workgroup size,
 // items per thread (tile = block * ipt keys) and the wave-level match used
@@ -128,5 +134,69 @@ int lds_class_block(int cls);
 hipError_t lds_sort_blocks_per_cu(int key_bits, bool has_values, int cls, int *blocks);
 hipError_t launch_lds_sort(int key_bits, bool has_values, const LdsSortArgs &a, uint32_t grid,
                            hipStream_t stream);
+
+// ---------------------------------------------------------------- learned configuration
+constexpr int kMlpPlaces = 8, kMlpEnc = 16, kMlpScalars = 3, kMlpH1 = 64, kMlpH2 = 64;
+constexpr int kMlpClasses = 12;
+constexpr int kMlpU = kMlpPlaces * kMlpEnc + kMlpScalars;           // 131
+constexpr int kMlpFeatures = kMlpPlaces * kRadix + kMlpScalars;     // 2051
+constexpr uint32_t kMlpSamples = 4096;
+constexpr int kOffWe = 0;
+constexpr int kOffBe = kOffWe + kRadix * kMlpEnc;
+constexpr int kOffW1 = kOffBe + kMlpEnc;
+constexpr int kOffB1 = kOffW1 + kMlpU * kMlpH1;
+constexpr int kOffW2 = kOffB1 + kMlpH1;
+constexpr int kOffB2 = kOffW2 + kMlpH1 * kMlpH2;
+constexpr int kOffW3 = kOffB2 + kMlpH2;
+constexpr int kOffB3 = kOffW3 + kMlpH2 * kMlpClasses;
+constexpr int kMlpParams = kOffB3 + kMlpClasses;                    // 17500
+
+struct FeatureArgs {
+  const void *keys;
+  uint64_t n;
+  int begin_bit;
+  int end_bit;
+  int places;
+  int has_values;
+  float *out;  // kMlpFeatures
+};
+hipError_t launch_features(int key_bits, const FeatureArgs &a, hipStream_t stream);
+
+struct InferArgs {
+  const float *params;
+  const float *x;        // kMlpFeatures
+  uint32_t class_mask;   // classes that may be chosen
+  float *out;            // kMlpClasses
+  int *choice;
+};
+hipError_t launch_infer(const InferArgs &a, hipStream_t stream);
+
+struct GemmArgs {
+  const float *A;
+  const float *B;
+  float *C;
+  const float *bias;  // may be NULL
+  const float *mask;  // may be NULL: zero C where mask <= 0 (same layout as C)
+  int M, N, K;
+  long a_rs, a_cs, b_rs, b_cs, c_rs;
+  int relu;
+};
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t stream);
+hipError_t launch_colsum(const float *dz, int rows, int cols, int rs, float *db,
+                         hipStream_t stream);
+hipError_t launch_assemble(const float *enc, const float *scalars, float *u, int batch,
+                           hipStream_t stream);
+hipError_t launch_split(const float *d_u, const float *enc, float *d_enc, int batch,
+                        hipStream_t stream);
+hipError_t launch_loss(const float *out, const float *y, const float *mask, int count,
+                       float *d_out, float *loss, hipStream_t stream);
+
+struct AdamArgs {
+  float *theta, *m, *v;
+  const float *grad;
+  int count;
+  float lr, beta1, beta2, eps, c1, c2;
+};
+hipError_t launch_adam(const AdamArgs &a, hipStream_t stream);
 
 }  // namespace onesweep

@@ -153,3 +153,45 @@ def test_segmented_temp_query_and_validation():
                                       ctypes.c_void_p(4096), ctypes.c_void_p(8192), None, None,
                                       100, None, 1, 32, 0, 32, 1, None,
                                       None) == ow.ERROR_INVALID_VALUE
+
+
+def test_learned_constants_match_the_oracle_and_need_no_gpu():
+    import paper_2206_01784_amd as ow
+    from oracle import mlp
+    header = open(HEADER).read()
+    for name, value in (("ONESWEEP_FEATURES", mlp.FEATURES),
+                        ("ONESWEEP_MODEL_CLASSES", mlp.C),
+                        ("ONESWEEP_MODEL_PARAMS", mlp.NUM_PARAMS)):
+        assert re.search(rf"#define {name} {value}\b", header), name
+    assert ow.library().onesweep_model_num_params() == mlp.NUM_PARAMS
+    assert (ow.FEATURES, ow.MODEL_CLASSES, ow.MODEL_PARAMS) == \
+        (mlp.FEATURES, mlp.C, mlp.NUM_PARAMS)
+    # a missing or foreign model file is rejected before any GPU work
+    h = ctypes.c_void_p()
+    assert ow.library().onesweep_model_load(b"/nonexistent/model.bin", 4,
+                                            ctypes.byref(h)) == ow.ERROR_INVALID_VALUE
+    import tempfile
+    with tempfile.NamedTemporaryFile(suffix=".bin") as f:
+        f.write(b"NOTAMODEL" * 100)
+        f.flush()
+        assert ow.library().onesweep_model_load(f.name.encode(), 4,
+                                                ctypes.byref(h)) == ow.ERROR_INVALID_VALUE
+    # no model: the default configuration, no GPU touched
+    cfg = ow.Config()
+    assert ow.library().onesweep_select_config(None, None, 1000, 32, 0, 32, 0,
+                                               ctypes.byref(cfg), None) == 0
+    assert (cfg.block_threads, cfg.items_per_thread) == (0, 0)
+
+
+def test_segmented_tuner_size_query_needs_no_gpu():
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    size = ctypes.c_size_t(0)
+    dummy = ctypes.c_void_p(4)
+    assert lib.onesweep_tune_segments(None, ctypes.byref(size), None, None, dummy, dummy,
+                                      1 << 20, None, 100, 32, 0, 32, 3, None, None) == 0
+    # the largest need over the candidates covers the default configuration
+    assert size.value >= ow.sort_segments_temp_bytes(1 << 20, 100, 32, True)
+    assert lib.onesweep_tune_segments(None, ctypes.byref(size), None, None, None, None,
+                                      1 << 20, None, 100, 32, 0, 32, 0, None,
+                                      None) == ow.ERROR_INVALID_VALUE

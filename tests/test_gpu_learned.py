@@ -1,0 +1,216 @@
+"""GPU parity of the learned configuration selector against the fp64 CPU
+oracle (oracle/mlp.py): features, the fused one-input forward pass, the
+batched training forward, gradients of every parameter block, Adam steps,
+model files, and selection feeding a bit-exact sort.
+
+Float tolerance: the kernels accumulate in float32 over at most 256 terms of
+magnitude below about 1 (sums of K products, K <= 256), so the rounding error
+of an output is below K * 2^-24 * sum|terms|, about 1.5e-5 of the largest
+magnitude involved; the tests allow 1e-4 of the largest reference magnitude
+of each block (plus 1e-7 absolute for entries that are exactly zero).
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workload as W
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ow():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2206_01784_amd as mod
+    return mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def close(got, want, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    scale = max(1e-30, float(np.abs(want).max()))
+    err = float(np.abs(got - want).max())
+    assert err <= RTOL * scale + 1e-7, (what, err, scale)
+
+
+def random_params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    flat = rng.normal(0.0, scale, size=M.NUM_PARAMS).astype(np.float32)
+    return flat
+
+
+def random_batch(seed, B):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((B, M.FEATURES), dtype=np.float32)
+    hist = rng.random((B, M.P, M.R)).astype(np.float32)
+    hist /= hist.sum(axis=2, keepdims=True)
+    x[:, : M.P * M.R] = hist.reshape(B, -1)
+    x[:, M.P * M.R:] = rng.random((B, M.S)).astype(np.float32)
+    y = rng.normal(0.0, 0.5, size=(B, M.C)).astype(np.float32)
+    mask = (rng.random((B, M.C)) < 0.8).astype(np.float32)
+    return x, y, mask
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("n", [1, 100, 4095, 4096, 4097, 100_003, 1 << 20])
+def test_features_match_oracle(ow, kb, n):
+    for dist in ("uniform", "zipf", "and3"):
+        keys = W.make_keys(dist, 40 + n % 7, n, kb)
+        for begin, end, vals in ((0, kb, False), (3, kb - 5, True), (8, 9, False)):
+            got = ow.features(dev(keys), begin, end, vals).cpu().numpy()
+            want = M.features(keys, begin, end, vals)
+            hist_err = np.abs(got[: M.P * M.R] - want[: M.P * M.R]).max()
+            assert hist_err <= 1e-7, (dist, n, begin, end, hist_err)
+            if n % 4096 == 0 or n > 4096:
+                # the sample is 4096 keys: every fraction is exact in float32
+                assert np.array_equal(got[: M.P * M.R], want[: M.P * M.R].astype(np.float32))
+            close(got[M.P * M.R:], want[M.P * M.R:], (dist, n, "scalars"))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_batched_forward_matches_oracle(ow, seed):
+    flat = random_params(seed)
+    x, _, _ = random_batch(seed + 10, 37)
+    m = ow.Model(max_batch=64)
+    m.set_params(flat)
+    got = m.forward(dev(x)).cpu().numpy()
+    want = M.forward(M.unflatten(flat.astype(np.float64)), x.astype(np.float64))["out"]
+    close(got, want, "forward")
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_fused_inference_matches_oracle(ow, seed):
+    flat = random_params(seed)
+    m = ow.Model(max_batch=4)
+    m.set_params(flat)
+    keys = W.uniform(seed, 300_000, 64)
+    feats = ow.features(dev(keys), 0, 64, True)
+    out, choice = m.infer(feats)
+    want = M.forward(M.unflatten(flat.astype(np.float64)),
+                     feats.cpu().numpy()[None, :].astype(np.float64))["out"][0]
+    close(out.cpu().numpy(), want, "infer")
+    for mask in ((1 << 12) - 1, 0b101010101010, 0b1):
+        _, choice = m.infer(feats, mask)
+        c = int(choice.cpu().numpy()[0])
+        allowed = [i for i in range(12) if (mask >> i) & 1]
+        assert c in allowed
+        best = min(allowed, key=lambda i: want[i])
+        # equal unless two predictions are closer than the tolerance
+        assert c == best or abs(want[c] - want[best]) <= RTOL * np.abs(want).max()
+    _, choice = m.infer(feats, 0)
+    assert int(choice.cpu().numpy()[0]) == -1
+
+
+@pytest.mark.parametrize("seed,B", [(6, 1), (7, 23), (8, 130)])
+def test_gradients_match_oracle(ow, seed, B):
+    flat = random_params(seed)
+    x, y, mask = random_batch(seed + 20, B)
+    m = ow.Model(max_batch=256)
+    m.set_params(flat)
+    loss, grad = m.gradients(dev(x), dev(y), dev(mask))
+    params = M.unflatten(flat.astype(np.float64))
+    acts = M.forward(params, x.astype(np.float64))
+    want = M.backward(params, acts, y.astype(np.float64), mask.astype(np.float64))
+    close(loss.cpu().numpy(), [M.loss(acts["out"], y, mask)], "loss")
+    g = M.unflatten(grad.cpu().numpy().astype(np.float64))
+    for name, _ in M.PARAM_SHAPES:
+        close(g[name], want[name], name)
+
+
+def test_adam_steps_match_oracle(ow):
+    """Each GPU step from the GPU's current parameters equals the oracle's
+    Adam step from those parameters (oracle gradients in fp64, oracle
+    moments carried along). Entries whose gradient is below 1e-3 of the
+    largest are dominated by the float32 rounding of the gradient itself;
+    for them only Adam's step bound |move| <= lr (first step) is checked."""
+    flat = random_params(9)
+    x, y, mask = random_batch(29, 64)
+    m = ow.Model(max_batch=64)
+    m.set_params(flat)
+    theta = flat.astype(np.float64)
+    mm = np.zeros_like(theta)
+    vv = np.zeros_like(theta)
+    lr = 1e-3
+    dx, dy, dmask = dev(x), dev(y), dev(mask)
+    for t in range(1, 4):
+        params = M.unflatten(theta)
+        acts = M.forward(params, x.astype(np.float64))
+        g = M.flatten(M.backward(params, acts, y.astype(np.float64), mask.astype(np.float64)))
+        want, mm, vv = M.adam(theta, g, mm, vv, t, lr=lr)
+        m.train_step(dx, dy, dmask, lr)
+        got = m.get_params().astype(np.float64)
+        big = np.abs(g) >= 1e-3 * np.abs(g).max()
+        move_err = np.abs((got - theta) - (want - theta))
+        assert float(move_err[big].max()) <= 0.01 * lr + 1e-7, (t, move_err[big].max())
+        if t == 1:
+            assert float(np.abs(got - theta).max()) <= lr * (1 + 1e-3) + 1e-7
+        theta = got
+
+
+def test_training_fits_a_teacher(ow):
+    """Targets from a fixed random network: 300 Adam steps cut the loss."""
+    teacher = random_params(11, scale=0.2)
+    x, _, _ = random_batch(31, 256)
+    y = M.forward(M.unflatten(teacher.astype(np.float64)), x.astype(np.float64))["out"]
+    y = y.astype(np.float32)
+    mask = np.ones_like(y)
+    m = ow.Model(max_batch=256)
+    m.set_params(random_params(12, scale=0.1))
+    dx, dy, dmask = dev(x), dev(y), dev(mask)
+    first = float(m.train_step(dx, dy, dmask, 3e-3).cpu())
+    for _ in range(300):
+        last = m.train_step(dx, dy, dmask, 3e-3)
+    last = float(last.cpu())
+    assert last < 0.1 * first, (first, last)
+
+
+def test_model_file_round_trip(ow):
+    flat = random_params(13)
+    m = ow.Model(max_batch=8)
+    m.set_params(flat)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.bin")
+        m.save(path)
+        m2 = ow.Model(max_batch=8, path=path)
+        assert np.array_equal(m2.get_params(), flat)
+        for c in range(ow.MODEL_CLASSES):
+            a, ma = m.class_config(c)
+            b, mb = m2.class_config(c)
+            assert (a.block_threads, a.items_per_thread, a.rank_algorithm, ma) == \
+                (b.block_threads, b.items_per_thread, b.rank_algorithm, mb)
+        raw = bytearray(open(path, "rb").read())
+        open(path, "wb").write(bytes(raw[:-4]))  # truncated
+        with pytest.raises(ow.OnesweepError):
+            ow.Model(path=path)
+
+
+@pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
+def test_selected_config_sorts_bit_exactly(ow, kb, vals):
+    m = ow.Model(max_batch=4)
+    m.set_params(random_params(14 + kb))
+    n = 200_003
+    keys = W.make_keys("and2", 50 + kb, n, kb)
+    v = np.arange(n, dtype=np.uint32)
+    cfg = m.select_config(dev(keys), 0, kb, vals)
+    assert ow.tile_items(kb, vals, cfg) > 0
+    if vals:
+        ko, vo = ow.sort_pairs(dev(keys), dev(v), config=cfg)
+        wk, wv = oracle.sort(keys, v)
+        assert np.array_equal(ko.cpu().numpy(), wk) and np.array_equal(vo.cpu().numpy(), wv)
+    else:
+        ko = ow.sort_keys(dev(keys), config=cfg)
+        assert np.array_equal(ko.cpu().numpy(), oracle.sort(keys)[0])
+    # no model: the library default (all zero fields)
+    d = ow.select_config(None, dev(keys), 0, kb, vals)
+    assert (d.block_threads, d.items_per_thread, d.rank_algorithm) == (0, 0, 0)
