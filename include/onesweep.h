@@ -100,7 +100,8 @@ typedef struct {
     int items_per_thread;    /* binning items per thread */
     int hist_blocks_per_cu;  /* histogram grid = CUs x this (persistent, tile-cyclic) */
     int rank_algorithm;      /* wave-level digit match: 0 default, 1 one ballot per
-                                digit bit, 2 LDS presence masks (same output) */
+                                digit bit, 2 LDS presence masks, 3 ballots with
+                                one LDS atomic per digit group (same output) */
     int segment_limits[3];   /* segmented sort only: longest segment sorted whole in
                                 LDS by the 64-, 256- and 1024-thread class; 0 =
                                 the class's capacity (512, 2048, 8192 keys), -1 =

@@ -94,7 +94,7 @@ def _check(code: int):
         raise OnesweepError(code, _lib.onesweep_last_error().decode())
 
 
-RANK_DEFAULT, RANK_BALLOT, RANK_PRESENCE = 0, 1, 2
+RANK_DEFAULT, RANK_BALLOT, RANK_PRESENCE, RANK_ATOMIC = 0, 1, 2, 3
 
 
 def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,

@@ -85,8 +85,8 @@ onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t
       return fail(ONESWEEP_ERROR_INVALID_VALUE, "hist_blocks_per_cu %d out of [0, 64]",
                   cfg->hist_blocks_per_cu);
     if (cfg->hist_blocks_per_cu != 0) r->hist_blocks_per_cu = cfg->hist_blocks_per_cu;
-    if (cfg->rank_algorithm < 0 || cfg->rank_algorithm > 2)
-      return fail(ONESWEEP_ERROR_INVALID_VALUE, "rank_algorithm %d not in [0, 2]",
+    if (cfg->rank_algorithm < 0 || cfg->rank_algorithm > 3)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "rank_algorithm %d not in [0, 3]",
                   cfg->rank_algorithm);
     if (cfg->rank_algorithm != 0) r->shape.rank = cfg->rank_algorithm - 1;
     r->trace = cfg->trace;

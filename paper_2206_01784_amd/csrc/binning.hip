@@ -34,7 +34,14 @@ namespace onesweep {
 //    per digit in LDS and reads the mask back. OR is order-independent, so
 //    the mask is exact whatever order the LDS serves the lanes in, and it
 //    costs a few instructions per batch instead of four per digit bit.
-enum RankAlgorithm : int { kRankBallot = 0, kRankPresence = 1 };
+//  - kRankAtomic: the ballot match, but the lowest lane of each digit group
+//    adds the group's size to the wave's LDS counter with an atomic that
+//    returns the previous count, and the group reads it from that lane
+//    afterwards. The batches' atomics do not wait on each other (a wave's
+//    LDS instructions execute in program order, which keeps the counts
+//    stable), so their latencies overlap instead of forming one chain of
+//    read-then-write per batch.
+enum RankAlgorithm : int { kRankBallot = 0, kRankPresence = 1, kRankAtomic = 2 };
 
 // Drop any global store whose index is not below n. Consistent counts never
 // produce such an index; the check only turns a logic error into a wrong
@@ -52,10 +59,14 @@ constexpr bool kCheckedStores = ONESWEEP_CHECKED_STORES != 0;
 constexpr int kLookback = ONESWEEP_LOOKBACK_WINDOW;
 
 // Occupancy target (waves per SIMD the register allocation must allow):
-// as high as the key registers permit without spilling.
+// as high as the key registers permit without spilling. 64-bit keys at 8
+// per thread still fit 64 registers (8 waves per SIMD, two 1024-thread
+// workgroups per CU); 32-bit keys at 16 per thread would spill there.
 template <typename K, int kIpt>
 constexpr int binning_waves_per_eu() {
-  return (kIpt * sizeof(K)) <= 32 ? 8 : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
+  return (kIpt * sizeof(K)) <= 32 || (sizeof(K) == 8 && kIpt == 8)
+             ? 8
+             : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
 }
 
 // kSeg: the tiles belong to the large segments of a segmented sort (each
@@ -107,7 +118,7 @@ __global__ void __launch_bounds__(kBlock)
   // workgroups beyond the actual count leave before taking a tile id, so the
   // ids handed out are exactly 0 .. tiles - 1.
   if constexpr (kSeg) {
-    if (blockIdx.x >= a.seg.plan->large_tiles) return;
+    if (a.seg.plan->error || blockIdx.x >= a.seg.plan->large_tiles) return;
   }
   {
     uint4 *z = reinterpret_cast<uint4 *>(s_rank);
@@ -157,6 +168,36 @@ __global__ void __launch_bounds__(kBlock)
   // wave's earlier keys with the same digit.
   uint32_t pos[kIpt];
   const uint32_t wave_table = static_cast<uint32_t>(wave) * kRadix * kEntryWords;
+  if constexpr (kRank == kRankAtomic) {
+    // Batch i's previous count is read back kDepth batches later, so only
+    // kDepth (prior, leader) pairs are live at a time.
+    constexpr int kDepth = kIpt < 3 ? kIpt : 3;
+    uint32_t prior[kIpt], leader[kIpt];
+#pragma unroll
+    for (int i = 0; i < kIpt + kDepth; ++i) {
+      if (i >= kDepth) {
+        const int r = i - kDepth;
+        pos[r] += __shfl(prior[r], static_cast<int>(leader[r]), kWave);
+      }
+      if (i >= kIpt) continue;
+      const uint32_t d = digit_of(key[i], shift, mask);
+      uint32_t peers_lo = ~0u, peers_hi = ~0u;
+#pragma unroll
+      for (int b = 0; b < kRadixBits; ++b) {
+        const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);  // 0 or -1
+        const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
+        peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
+        peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
+      }
+      pos[i] = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+      leader[i] = peers_lo != 0u ? static_cast<uint32_t>(__builtin_ctz(peers_lo))
+                                 : 32u + static_cast<uint32_t>(__builtin_ctz(peers_hi));
+      prior[i] = 0u;
+      if (pos[i] == 0u)
+        prior[i] = atomicAdd(&s_rank[wave_table + d],
+                             static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi)));
+    }
+  } else {
 #pragma unroll
   for (int i = 0; i < kIpt; ++i) {
     const uint32_t d = digit_of(key[i], shift, mask);
@@ -193,6 +234,7 @@ __global__ void __launch_bounds__(kBlock)
       s_rank[e] = next;
     }
     __builtin_amdgcn_wave_barrier();
+  }
   }
   __syncthreads();
 
@@ -363,7 +405,27 @@ __global__ void __launch_bounds__(kBlock)
   X(uint64_t, true, 256, 16, 1)       \
   X(uint64_t, true, 512, 8, 1)        \
   X(uint64_t, true, 512, 12, 1)       \
-  X(uint64_t, true, 1024, 8, 1)
+  X(uint64_t, true, 1024, 8, 1)       \
+  X(uint32_t, false, 256, 8, 2)       \
+  X(uint32_t, false, 256, 16, 2)      \
+  X(uint32_t, false, 512, 16, 2)      \
+  X(uint32_t, false, 512, 12, 2)      \
+  X(uint32_t, false, 1024, 8, 2)      \
+  X(uint32_t, true, 256, 8, 2)        \
+  X(uint32_t, true, 256, 16, 2)       \
+  X(uint32_t, true, 512, 16, 2)       \
+  X(uint32_t, true, 512, 12, 2)       \
+  X(uint32_t, true, 1024, 8, 2)       \
+  X(uint64_t, false, 256, 8, 2)       \
+  X(uint64_t, false, 256, 16, 2)      \
+  X(uint64_t, false, 512, 8, 2)       \
+  X(uint64_t, false, 512, 12, 2)      \
+  X(uint64_t, false, 1024, 8, 2)      \
+  X(uint64_t, true, 256, 8, 2)        \
+  X(uint64_t, true, 256, 16, 2)       \
+  X(uint64_t, true, 512, 8, 2)        \
+  X(uint64_t, true, 512, 12, 2)       \
+  X(uint64_t, true, 1024, 8, 2)
 
 // Shapes also built for the large segments of a segmented sort.
 #define ONESWEEP_SEGMENT_BINNING_SHAPES(X) \

@@ -3,11 +3,11 @@
 // whole batch can be captured in one HIP graph) and driven by device-side
 // offsets, so the host never learns the segment lengths.
 //
-//  - classify: one workgroup validates the offsets and assigns every
-//    non-empty segment to a class by length: three classes small enough to be
-//    sorted inside one workgroup's LDS (64, 256 or 1024 threads, 8 keys per
-//    thread) and a "large" class. Each large segment is cut into binning tiles
-//    whose descriptors are written in segment order.
+//  - classify: one thread per segment validates its offsets and assigns the
+//    segment to a class by length: three classes small enough to be sorted
+//    inside one workgroup's LDS (64, 256 or 1024 threads, 8 keys per thread)
+//    and a "large" class. Each large segment is cut into binning tiles whose
+//    descriptors are consecutive.
 //  - LDS sort: one workgroup per segment loads it once, runs the LSD passes
 //    over 8-bit digits in LDS with the same wave64 multi-split ranking as the
 //    binning kernel, and writes it once.
@@ -23,101 +23,101 @@ namespace onesweep {
 // ---------------------------------------------------------------- classify
 constexpr int kClassifyBlock = 1024;
 
+// Clears the plan (counts, error word) and the binning tile counters; the
+// classify workgroups then accumulate into the plan with atomics.
+__global__ void __launch_bounds__(64) segment_init_kernel(SegmentPlan *plan,
+                                                          uint32_t *tile_counters) {
+  const int tid = threadIdx.x;
+  if (tid < kMaxPlaces) tile_counters[tid] = 0u;
+  reinterpret_cast<uint32_t *>(plan)[tid] = 0u;
+}
+
+// One thread per segment. A workgroup counts its segments per class and its
+// large segments' tiles, reserves that many list entries and tiles with one
+// atomic per class, and writes the entries (list order across workgroups
+// is arbitrary; every segment is sorted on its own, so order does not
+// matter, and each large segment's tiles stay consecutive).
 __global__ void __launch_bounds__(kClassifyBlock) classify_kernel(ClassifyArgs a) {
   constexpr int kWaves = kClassifyBlock / kWave;
   constexpr int kQ = kSegClasses + 2;  // per-class counts, then tiles
   __shared__ uint32_t s_wave[kWaves][kQ];
+  __shared__ uint32_t s_base[kQ];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  if (tid < kMaxPlaces) a.tile_counters[tid] = 0u;
-
-  uint32_t run[kQ];
-#pragma unroll
-  for (int c = 0; c < kQ; ++c) run[c] = 0u;
-  bool bad = false;
   const uint32_t T = a.tile_items;
-
-  for (uint32_t base = 0; base < a.num_segments; base += kClassifyBlock) {
-    const uint32_t s = base + tid;
-    uint32_t cls = kQ, tiles = 0u, lo = 0u, len = 0u;
-    if (s < a.num_segments) {
-      lo = a.offsets[s];
-      const uint32_t hi = a.offsets[s + 1];
-      if (hi < lo || hi > a.n) {
-        bad = true;
-      } else {
-        len = hi - lo;
-        if (len > 0u) {
-          cls = kSegClasses;
-          for (int c = kSegClasses - 1; c >= 0; --c)
-            if (len <= a.limit[c]) cls = c;
-          if (cls == kSegClasses) tiles = (len + T - 1u) / T;
-        }
+  const uint32_t s = blockIdx.x * kClassifyBlock + tid;
+  bool bad = false;
+  uint32_t cls = kQ, tiles = 0u, lo = 0u, len = 0u;
+  if (s < a.num_segments) {
+    lo = a.offsets[s];
+    const uint32_t hi = a.offsets[s + 1];
+    if (hi < lo || hi > a.n) {
+      bad = true;
+    } else {
+      len = hi - lo;
+      if (len > 0u) {
+        cls = kSegClasses;
+        for (int c = kSegClasses - 1; c >= 0; --c)
+          if (len <= a.limit[c]) cls = c;
+        if (cls == kSegClasses) tiles = (len + T - 1u) / T;
       }
     }
-    // Block-wide exclusive prefix of the class flags and of the tile counts.
-    uint32_t rank = 0u;
-#pragma unroll
-    for (int c = 0; c <= kSegClasses; ++c) {
-      const uint64_t m = __builtin_amdgcn_ballot_w64(cls == static_cast<uint32_t>(c));
-      if (cls == static_cast<uint32_t>(c)) rank = count_below(m);
-      if (lane == 0) s_wave[wave][c] = static_cast<uint32_t>(__popcll(m));
-    }
-    uint32_t incl = tiles;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t t = __shfl_up(incl, off, kWave);
-      if (lane >= off) incl += t;
-    }
-    if (lane == kWave - 1) s_wave[wave][kQ - 1] = incl;
-    __syncthreads();
-    uint32_t pre[kQ];
-#pragma unroll
-    for (int c = 0; c < kQ; ++c) {
-      uint32_t before = 0u, all = 0u;
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t v = s_wave[w][c];
-        if (w < wave) before += v;
-        all += v;
-      }
-      pre[c] = run[c] + before;
-      run[c] += all;
-    }
-    if (cls < static_cast<uint32_t>(kSegClasses)) {
-      const uint32_t idx = pre[cls] + rank;
-      if (idx < a.capacity[cls]) a.lists[cls][idx] = s;
-    } else if (cls == static_cast<uint32_t>(kSegClasses)) {
-      const uint32_t li = pre[kSegClasses] + rank;
-      const uint32_t first = pre[kQ - 1] + incl - tiles;
-      for (uint32_t k = 0; k < tiles; ++k) {
-        if (first + k >= a.max_tiles) break;  // only reachable with invalid offsets
-        const uint32_t b = lo + k * T;
-        a.tile_info[first + k] = make_uint4(b, min(T, len - k * T), lo, li);
-      }
-    }
-    __syncthreads();  // s_wave is rewritten by the next chunk
   }
-  if (tid == 0) {
-    if (a.offsets[0] != 0u || a.offsets[a.num_segments] != a.n) bad = true;
-    if (run[kSegClasses] > a.max_large || run[kQ - 1] > a.max_tiles) bad = true;
-    for (int c = 0; c < kSegClasses; ++c)
-      if (run[c] > a.capacity[c]) bad = true;
+  if (s == 0 && (a.offsets[0] != 0u || a.offsets[a.num_segments] != a.n)) bad = true;
+  uint32_t rank = 0u;
+#pragma unroll
+  for (int c = 0; c <= kSegClasses; ++c) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(cls == static_cast<uint32_t>(c));
+    if (cls == static_cast<uint32_t>(c)) rank = count_below(m);
+    if (lane == 0) s_wave[wave][c] = static_cast<uint32_t>(__popcll(m));
   }
-  const int invalid = __syncthreads_or(bad);
-  if (tid == 0) {
-    SegmentPlan p;
-    p.error = invalid ? 1u : 0u;
-    for (int c = 0; c <= kSegClasses; ++c) p.count[c] = invalid ? 0u : run[c];
-    p.large_tiles = invalid ? 0u : run[kQ - 1];
-    for (int i = 0; i < 58; ++i) p.pad[i] = 0u;
-    *a.plan = p;
+  uint32_t incl = tiles;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += t;
+  }
+  if (lane == kWave - 1) s_wave[wave][kQ - 1] = incl;
+  const int any_bad = __syncthreads_or(bad);
+  if (tid < kQ) {
+    uint32_t total = 0u;
+    for (int w = 0; w < kWaves; ++w) total += s_wave[w][tid];
+    uint32_t *counter = tid < kQ - 1 ? &a.plan->count[tid] : &a.plan->large_tiles;
+    s_base[tid] = total ? atomicAdd(counter, total) : 0u;
+  }
+  if (tid == 0 && any_bad) atomicOr(&a.plan->error, 1u);
+  __syncthreads();
+  uint32_t pre[kQ];
+#pragma unroll
+  for (int c = 0; c < kQ; ++c) {
+    uint32_t before = 0u;
+    for (int w = 0; w < wave; ++w) before += s_wave[w][c];
+    pre[c] = s_base[c] + before;
+  }
+  if (cls < static_cast<uint32_t>(kSegClasses)) {
+    const uint32_t idx = pre[cls] + rank;
+    if (idx < a.capacity[cls]) a.lists[cls][idx] = s;
+    else atomicOr(&a.plan->error, 1u);  // only reachable with invalid offsets
+  } else if (cls == static_cast<uint32_t>(kSegClasses)) {
+    const uint32_t li = pre[kSegClasses] + rank;
+    const uint32_t first = pre[kQ - 1] + incl - tiles;
+    if (li >= a.max_large || first + tiles > a.max_tiles) {
+      atomicOr(&a.plan->error, 1u);  // only reachable with invalid offsets
+    } else {
+      for (uint32_t k = 0; k < tiles; ++k)
+        a.tile_info[first + k] = make_uint4(lo + k * T, min(T, len - k * T), lo, li);
+    }
   }
 }
 
 hipError_t launch_classify(const ClassifyArgs &a, hipStream_t stream) {
-  hipLaunchKernelGGL(classify_kernel, dim3(1), dim3(kClassifyBlock), 0, stream, a);
+  hipLaunchKernelGGL(segment_init_kernel, dim3(1), dim3(64), 0, stream, a.plan, a.tile_counters);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.num_segments == 0) return e;
+  const uint32_t grid = (a.num_segments + kClassifyBlock - 1) / kClassifyBlock;
+  hipLaunchKernelGGL(classify_kernel, dim3(grid), dim3(kClassifyBlock), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(256) segment_clear_kernel(SegmentClearArgs a) 
   const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
   const size_t first = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+  if (a.plan->error) return;
   const size_t status_vecs = static_cast<size_t>(a.plan->large_tiles) * (kRadix / 4);
   for (int j = 0; j < a.places; ++j) {
     uint4 *row = reinterpret_cast<uint4 *>(a.status + j * a.status_words_per_place);
@@ -166,19 +167,29 @@ __global__ void __launch_bounds__(256) segment_histogram_kernel(SegmentHistArgs 
     masks[j] = j < places ? ((1u << (hi - lo)) - 1u) : 0u;
   }
   uint32_t *my_hist = s_hist + (tid % kCopies);
-  const uint32_t tiles = a.plan->large_tiles;
+  const uint32_t tiles = a.plan->error ? 0u : a.plan->large_tiles;
   for (int i = tid; i < places * kRadix * kCopies; i += 256) s_hist[i] = 0u;
   __syncthreads();
   for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     const uint4 info = a.tile_info[t];
-    for (uint32_t i = tid; i < info.y; i += 256) {
-      const K k = keys[info.x + i];
+    constexpr int kBatch = 8;  // independent loads in flight per thread
+    for (uint32_t base = 0; base < info.y; base += 256 * kBatch) {
+      K k[kBatch];
 #pragma unroll
-      for (int j = 0; j < kMaxP; ++j)
-        if (j < places)
-          atomicAdd(&my_hist[(j * kRadix + (static_cast<uint32_t>(k >> shifts[j]) & masks[j])) *
-                             kCopies],
-                    1u);
+      for (int b = 0; b < kBatch; ++b) {
+        const uint32_t i = base + b * 256 + tid;
+        k[b] = i < info.y ? keys[info.x + i] : K(0);
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if (base + b * 256 + tid >= info.y) continue;
+#pragma unroll
+        for (int j = 0; j < kMaxP; ++j)
+          if (j < places)
+            atomicAdd(&my_hist[(j * kRadix + (static_cast<uint32_t>(k[b] >> shifts[j]) & masks[j])) *
+                               kCopies],
+                      1u);
+      }
     }
     __syncthreads();
     uint32_t *dst = a.hist + static_cast<size_t>(info.w) * places * kRadix;
@@ -202,7 +213,7 @@ __global__ void __launch_bounds__(256) segment_scan_kernel(uint32_t *hist,
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
   const uint32_t waves = gridDim.x * (256 / kWave);
-  const uint32_t rows = plan->count[kSegClasses] * static_cast<uint32_t>(places);
+  const uint32_t rows = plan->error ? 0u : plan->count[kSegClasses] * static_cast<uint32_t>(places);
   for (uint32_t row = wave; row < rows; row += waves) {
     uint4 *p = reinterpret_cast<uint4 *>(hist + static_cast<size_t>(row) * kRadix) + lane;
     const uint4 v = *p;
@@ -236,7 +247,7 @@ hipError_t launch_segment_scan(uint32_t *hist, const SegmentPlan *plan, int plac
 // Copy of the large segments' keys (and values) from the temporary buffer to
 // the output, for an odd number of passes with the input aliasing the output.
 __global__ void __launch_bounds__(256) segment_copy_kernel(SegmentCopyArgs a) {
-  const uint32_t tiles = a.plan->large_tiles;
+  const uint32_t tiles = a.plan->error ? 0u : a.plan->large_tiles;
   for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     const uint4 info = a.tile_info[t];
     if (a.key_bytes == 4) {
@@ -270,8 +281,17 @@ hipError_t launch_segment_copy(const SegmentCopyArgs &a, uint32_t grid, hipStrea
 // that start past the segment's end take no part; the last partial batch is
 // padded with all-ones keys, which rank after every real key and so stay in
 // the slots past the end.
+// The 1024-thread class with 32-bit keys is held to 64 registers so two
+// workgroups fit a CU.
+template <typename K, int kBlock>
+constexpr int lds_sort_waves_per_eu() {
+  return kBlock >= 1024 && sizeof(K) == 4 ? 8 : 4;
+}
+
 template <typename K, bool kVals, int kBlock, int kIpt>
-__global__ void __launch_bounds__(kBlock) lds_sort_kernel(LdsSortArgs a) {
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(lds_sort_waves_per_eu<K, kBlock>())))
+    lds_sort_kernel(LdsSortArgs a) {
   constexpr int kWaves = kBlock / kWave;
   constexpr int kTile = kBlock * kIpt;
   constexpr int kWaveItems = kWave * kIpt;
@@ -290,7 +310,7 @@ __global__ void __launch_bounds__(kBlock) lds_sort_kernel(LdsSortArgs a) {
   const int wave = tid / kWave;
   const K *__restrict__ kin = static_cast<const K *>(a.keys_in);
   K *__restrict__ kout = static_cast<K *>(a.keys_out);
-  const uint32_t count = a.plan->count[a.cls];
+  const uint32_t count = a.plan->error ? 0u : a.plan->count[a.cls];
   const uint32_t *list = a.list;
   const uint32_t wave_first = static_cast<uint32_t>(wave) * kWaveItems;
 

@@ -61,12 +61,12 @@ def test_histogram_empty_and_unaligned(ow):
 # ------------------------------------------------------------------ phase 3 (one pass)
 
 SHAPES = {
-    (32, False): [(256, 16), (512, 16), (512, 12), (1024, 8)],
-    (32, True): [(256, 16), (512, 16), (512, 12), (1024, 8)],
-    (64, False): [(256, 16), (512, 8), (512, 12), (1024, 8)],
-    (64, True): [(256, 16), (512, 8), (512, 12), (1024, 8)],
+    (32, False): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8)],
+    (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8)],
+    (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8)],
+    (64, True): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8)],
 }
-RANKS = (1, 2)  # one ballot per digit bit; LDS presence masks
+RANKS = (1, 2, 3)  # one ballot per digit bit; LDS presence masks; ballots + LDS atomics
 
 
 @pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
