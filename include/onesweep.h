@@ -301,10 +301,12 @@ onesweep_status_t onesweep_model_train_step(onesweep_model_t *model, const float
                                             const float *d_scalars, const float *d_y,
                                             const float *d_mask, int batch, float lr,
                                             float *d_loss, onesweep_stream_t stream);
-/* Configuration for sorting these keys: features, one forward pass and the
- * best class that applies to key_bits, then a synchronisation of `stream`
- * to read the choice. A NULL model (or n == 0) yields the library default
- * (all fields 0). cfg_out->trace is NULL. */
+/* Configuration for sorting these keys: features and one forward pass in a
+ * single kernel, the best class that applies to key_bits, then a
+ * synchronisation of `stream` to read the choice (written by the kernel to
+ * pinned host memory). A NULL model (or n == 0) yields the library default
+ * (all fields 0). cfg_out->trace is NULL. Calls on one model must not
+ * overlap. */
 onesweep_status_t onesweep_select_config(const onesweep_model_t *model, const void *d_keys,
                                          size_t n, int key_bits, int begin_bit, int end_bit,
                                          int has_values, onesweep_config_t *cfg_out,

@@ -117,4 +117,57 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
   return static_cast<uint32_t>(key >> shift) & mask;
 }
 
+// Inclusive sum over the lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+  const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off, kWave);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+// In-place exclusive scan of a table of per-wave digit counts,
+// table[w * 256 + d], taken in digit-major order: afterwards entry (w, d)
+// holds the number of keys with a smaller digit plus the keys of digit d in
+// waves before w, i.e. the position in the workgroup's digit-sorted order of
+// wave w's first key with digit d. Every thread of the workgroup owns four
+// consecutive entries of that order, so the scan costs one LDS read and one
+// write per entry and a workgroup-wide sum of per-thread totals. The caller
+// synchronises before (table complete) and after (table rewritten);
+// s_wave_sum holds kBlock / 64 words.
+template <int kBlock>
+__device__ __forceinline__ void digit_major_exclusive_scan(uint32_t *table,
+                                                           uint32_t *s_wave_sum) {
+  constexpr int kWaves = kBlock / kWave;
+  static_assert(kWaves * kRadix == 4 * kBlock, "four entries per thread");
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  uint32_t c[4], ex[4], sum = 0u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int f = 4 * tid + k;
+    c[k] = table[(f % kWaves) * kRadix + f / kWaves];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ex[k] = sum;
+    sum += c[k];
+  }
+  const uint32_t incl = wave_inclusive_sum(sum);
+  uint32_t base = incl - sum;
+  if constexpr (kWaves > 1) {
+    if (lane == kWave - 1) s_wave_sum[wave] = incl;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) base += s_wave_sum[w];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int f = 4 * tid + k;
+    table[(f % kWaves) * kRadix + f / kWaves] = base + ex[k];
+  }
+}
+
 }  // namespace onesweep

@@ -171,6 +171,21 @@ struct InferArgs {
 };
 hipError_t launch_infer(const InferArgs &a, hipStream_t stream);
 
+struct SelectArgs {
+  const float *params;
+  const void *keys;
+  uint64_t n;
+  int begin_bit;
+  int end_bit;
+  int places;
+  int has_values;
+  uint32_t class_mask;
+  float *out;         // kMlpClasses
+  int *choice;        // device
+  int *host_choice;   // mapped pinned host memory, may be NULL
+};
+hipError_t launch_select(int key_bits, const SelectArgs &a, hipStream_t stream);
+
 struct GemmArgs {
   const float *A;
   const float *B;

@@ -125,6 +125,132 @@ hipError_t launch_infer(const InferArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- selection
+// Features and the forward pass of one input fused into one workgroup of
+// 1024 threads, everything staged in LDS: the parameters (70 KB, coalesced
+// loads issued together with the key samples), the sampled digit counts, and
+// each layer's activations. Dot products are split over groups of threads
+// whose lanes read consecutive weights; partial sums meet in LDS. The result
+// (outputs and the chosen class) equals infer_kernel's up to float32
+// summation order.
+template <typename K>
+__global__ void __launch_bounds__(1024) select_kernel(SelectArgs a) {
+  constexpr int kThreads = 1024;
+  constexpr int kEncOut = kMlpPlaces * kMlpEnc;  // 128
+  __shared__ float s_p[kMlpParams];
+  __shared__ uint32_t s_hist[kMlpPlaces * kRadix];
+  __shared__ float s_part[kThreads];
+  __shared__ float s_u[kMlpU];
+  __shared__ float s_h1[kMlpH1];
+  __shared__ float s_h2[kMlpH2];
+  __shared__ float s_out[kMlpClasses];
+  const int tid = threadIdx.x;
+  const K *keys = static_cast<const K *>(a.keys);
+  for (int i = tid; i < kMlpPlaces * kRadix; i += kThreads) s_hist[i] = 0u;
+  for (int i = tid; i < kMlpParams; i += kThreads) s_p[i] = a.params[i];
+  const uint64_t n = a.n;
+  const uint32_t m = n < kMlpSamples ? static_cast<uint32_t>(n) : kMlpSamples;
+  K k[kMlpSamples / kThreads];
+#pragma unroll
+  for (int r = 0; r < static_cast<int>(kMlpSamples / kThreads); ++r) {
+    const uint32_t i = tid + r * kThreads;
+    k[r] = i < m ? keys[static_cast<uint64_t>(i) * n / m] : K(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < static_cast<int>(kMlpSamples / kThreads); ++r) {
+    if (static_cast<uint32_t>(tid + r * kThreads) >= m) continue;
+    for (int j = 0; j < a.places; ++j) {
+      const int lo = a.begin_bit + j * kRadixBits;
+      const int width = min(kRadixBits, a.end_bit - lo);
+      atomicAdd(&s_hist[j * kRadix + (static_cast<uint32_t>(k[r] >> lo) & ((1u << width) - 1u))],
+                1u);
+    }
+  }
+  __syncthreads();
+  const float *We = s_p + kOffWe, *be = s_p + kOffBe, *W1 = s_p + kOffW1, *b1 = s_p + kOffB1;
+  const float *W2 = s_p + kOffW2, *b2 = s_p + kOffB2, *W3 = s_p + kOffW3, *b3 = s_p + kOffB3;
+  const float fm = static_cast<float>(m);
+  {
+    // encoder: output o = (place o / 16, unit o % 16), 8 parts of 32 bins
+    const int o = tid % kEncOut, part = tid / kEncOut;
+    const int j = o / kMlpEnc, u = o % kMlpEnc;
+    float acc = 0.0f;
+    for (int v = part * 32; v < part * 32 + 32; ++v) {
+      const float x = m ? __fdiv_rn(static_cast<float>(s_hist[j * kRadix + v]), fm) : 0.0f;
+      acc = fmaf(x, We[v * kMlpEnc + u], acc);
+    }
+    s_part[part * kEncOut + o] = acc;
+  }
+  __syncthreads();
+  if (tid < kEncOut) {
+    float acc = 0.0f;
+    for (int part = 0; part < kThreads / kEncOut; ++part) acc += s_part[part * kEncOut + tid];
+    s_u[tid] = fmaxf(acc + be[tid % kMlpEnc], 0.0f);
+  } else if (tid == kEncOut) {
+    s_u[kEncOut + 0] = n ? log2f(static_cast<float>(n)) / 32.0f : 0.0f;
+    s_u[kEncOut + 1] = static_cast<float>(sizeof(K) * 8) / 64.0f;
+    s_u[kEncOut + 2] = a.has_values ? 1.0f : 0.0f;
+  }
+  __syncthreads();
+  {
+    // layer 1: output o, 16 parts striding over the 131 inputs
+    const int o = tid % kMlpH1, part = tid / kMlpH1;
+    float acc = 0.0f;
+    for (int i = part; i < kMlpU; i += kThreads / kMlpH1) acc = fmaf(s_u[i], W1[i * kMlpH1 + o], acc);
+    s_part[part * kMlpH1 + o] = acc;
+  }
+  __syncthreads();
+  if (tid < kMlpH1) {
+    float acc = b1[tid];
+    for (int part = 0; part < kThreads / kMlpH1; ++part) acc += s_part[part * kMlpH1 + tid];
+    s_h1[tid] = fmaxf(acc, 0.0f);
+  }
+  __syncthreads();
+  {
+    const int o = tid % kMlpH2, part = tid / kMlpH2;
+    float acc = 0.0f;
+    for (int i = part; i < kMlpH1; i += kThreads / kMlpH2) acc = fmaf(s_h1[i], W2[i * kMlpH2 + o], acc);
+    s_part[part * kMlpH2 + o] = acc;
+  }
+  __syncthreads();
+  if (tid < kMlpH2) {
+    float acc = b2[tid];
+    for (int part = 0; part < kThreads / kMlpH2; ++part) acc += s_part[part * kMlpH2 + tid];
+    s_h2[tid] = fmaxf(acc, 0.0f);
+  }
+  __syncthreads();
+  if (tid < kMlpClasses * 16) {
+    const int o = tid % kMlpClasses, part = tid / kMlpClasses;
+    float acc = 0.0f;
+    for (int i = part; i < kMlpH2; i += 16) acc = fmaf(s_h2[i], W3[i * kMlpClasses + o], acc);
+    s_part[part * kMlpClasses + o] = acc;
+  }
+  __syncthreads();
+  if (tid < kMlpClasses) {
+    float acc = b3[tid];
+    for (int part = 0; part < 16; ++part) acc += s_part[part * kMlpClasses + tid];
+    s_out[tid] = acc;
+    a.out[tid] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int best = -1;
+    for (int c = 0; c < kMlpClasses; ++c)
+      if (((a.class_mask >> c) & 1u) && (best < 0 || s_out[c] < s_out[best])) best = c;
+    *a.choice = best;
+    if (a.host_choice) *a.host_choice = best;
+  }
+}
+
+hipError_t launch_select(int key_bits, const SelectArgs &a, hipStream_t stream) {
+  if (key_bits == 32)
+    hipLaunchKernelGGL(select_kernel<uint32_t>, dim3(1), dim3(1024), 0, stream, a);
+  else
+    hipLaunchKernelGGL(select_kernel<uint64_t>, dim3(1), dim3(1024), 0, stream, a);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- training
 // C[i][j] = epilogue(sum_k A(i, k) B(k, j)) for i < M, j < N, with
 // A(i, k) = A[i * a_rs + k * a_cs] and B(k, j) = B[k * b_rs + j * b_cs], so

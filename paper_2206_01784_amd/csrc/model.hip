@@ -44,6 +44,8 @@ struct onesweep_model {
   float *enc, *u, *h1, *h2, *out, *d_out, *d_h2, *d_h1, *d_u, *d_enc;
   float *x1, *infer_out, *loss;
   int *choice;
+  int *host_choice;      // pinned, mapped host memory the selection kernel writes
+  int *host_choice_dev;  // its device address
   int step;
   ModelClass classes[kMlpClasses];
 };
@@ -93,10 +95,15 @@ onesweep_status_t create(int max_batch, onesweep_model **out) {
     return hip_fail(e, "model allocation");
   }
   e = hipMemset(m->block, 0, model_floats(max_batch) * sizeof(float));
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&m->host_choice), 64,
+                                         hipHostMallocMapped);
+  if (e == hipSuccess)
+    e = hipHostGetDevicePointer(reinterpret_cast<void **>(&m->host_choice_dev), m->host_choice, 0);
   if (e != hipSuccess) {
+    if (m->host_choice) (void)hipHostFree(m->host_choice);
     (void)hipFree(m->block);
     delete m;
-    return hip_fail(e, "model clear");
+    return hip_fail(e, "model allocation");
   }
   m->max_batch = max_batch;
   float *p = static_cast<float *>(m->block);
@@ -236,6 +243,7 @@ onesweep_status_t onesweep_model_create(int max_batch, onesweep_model_t **model)
 void onesweep_model_free(onesweep_model_t *model) {
   if (!model) return;
   (void)hipFree(model->block);
+  if (model->host_choice) (void)hipHostFree(model->host_choice);
   delete model;
 }
 
@@ -469,18 +477,30 @@ onesweep_status_t onesweep_select_config(const onesweep_model_t *m, const void *
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "key_bits %d is not 32 or 64", key_bits);
   memset(cfg_out, 0, sizeof(*cfg_out));
   if (!m || n == 0) return ONESWEEP_SUCCESS;  // the library's default configuration
-  onesweep_status_t st = onesweep_features(d_keys, n, key_bits, begin_bit, end_bit, has_values,
-                                           m->x1, stream);
-  if (st) return st;
+  if (begin_bit < 0 || begin_bit > end_bit || end_bit > key_bits)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "bit range [%d, %d) invalid", begin_bit, end_bit);
+  if (!d_keys || (reinterpret_cast<uintptr_t>(d_keys) & (key_bits / 8 - 1)))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_keys NULL or not aligned to the key size");
   unsigned mask = 0;
   for (int c = 0; c < kMlpClasses; ++c)
     if (m->classes[c].key_bits_mask & (key_bits == 32 ? 1 : 2)) mask |= 1u << c;
-  if ((st = onesweep_model_infer(m, m->x1, mask, m->infer_out, m->choice, stream))) return st;
-  int choice = -1;
+  SelectArgs a{};
+  a.params = m->params;
+  a.keys = d_keys;
+  a.n = n;
+  a.begin_bit = begin_bit;
+  a.end_bit = end_bit;
+  a.places = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+  a.has_values = has_values ? 1 : 0;
+  a.class_mask = mask;
+  a.out = m->infer_out;
+  a.choice = m->choice;
+  a.host_choice = m->host_choice_dev;
+  *m->host_choice = -1;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  MLP_TRY(hipMemcpyAsync(&choice, m->choice, sizeof(int), hipMemcpyDeviceToHost, s),
-          "hipMemcpyAsync");
+  MLP_TRY(launch_select(key_bits, a, s), "select");
   MLP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  const int choice = *static_cast<volatile int *>(m->host_choice);
   if (choice < 0 || choice >= kMlpClasses) return ONESWEEP_SUCCESS;  // no class applies
   return onesweep_model_class(m, choice, cfg_out, nullptr);
 }

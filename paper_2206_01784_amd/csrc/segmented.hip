@@ -295,13 +295,10 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int kWaves = kBlock / kWave;
   constexpr int kTile = kBlock * kIpt;
   constexpr int kWaveItems = kWave * kIpt;
-  constexpr int kScanThreads = kBlock < kRadix ? kBlock : kRadix;
-  constexpr int kDigitsPerThread = kRadix / kScanThreads;
-  constexpr int kScanWaves = kScanThreads / kWave;
   constexpr size_t kDataBytes = kTile * (sizeof(K) > 4 ? sizeof(K) : 4);
   __shared__ __attribute__((aligned(16))) unsigned char s_data[kDataBytes];
   __shared__ uint32_t s_cnt[kWaves * kRadix];
-  __shared__ uint32_t s_wave_sum[kScanWaves];
+  __shared__ uint32_t s_wave_sum[kWaves];
   K *s_keys = reinterpret_cast<K *>(s_data);
   uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_data);
 
@@ -356,44 +353,8 @@ __global__ void __launch_bounds__(kBlock)
         }
       }
       __syncthreads();
-      // Digit starts: per digit an exclusive sum over waves, then over digits.
-      uint32_t excl[kDigitsPerThread];
-      uint32_t start = 0u;
-      if (tid < kScanThreads) {
-        uint32_t thread_total = 0u;
-#pragma unroll
-        for (int dd = 0; dd < kDigitsPerThread; ++dd) {
-          const int d = tid * kDigitsPerThread + dd;
-          uint32_t run = 0u;
-#pragma unroll
-          for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c = s_cnt[w * kRadix + d];
-            s_cnt[w * kRadix + d] = run;
-            run += c;
-          }
-          excl[dd] = thread_total;
-          thread_total += run;
-        }
-        uint32_t incl = thread_total;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-          const uint32_t t = __shfl_up(incl, off, kWave);
-          if (lane >= off) incl += t;
-        }
-        if (kScanWaves > 1 && lane == kWave - 1) s_wave_sum[wave] = incl;
-        start = incl - thread_total;
-      }
-      if constexpr (kScanWaves > 1) __syncthreads();
-      if (tid < kScanThreads) {
-        if constexpr (kScanWaves > 1)
-          for (int w = 0; w < wave; ++w) start += s_wave_sum[w];
-#pragma unroll
-        for (int dd = 0; dd < kDigitsPerThread; ++dd) {
-          const int d = tid * kDigitsPerThread + dd;
-#pragma unroll
-          for (int w = 0; w < kWaves; ++w) s_cnt[w * kRadix + d] += start + excl[dd];
-        }
-      }
+      // Digit starts: exclusive scan of the counts in (digit, wave) order.
+      digit_major_exclusive_scan<kBlock>(s_cnt, s_wave_sum);
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < kIpt; ++i)

@@ -214,3 +214,41 @@ def test_selected_config_sorts_bit_exactly(ow, kb, vals):
     # no model: the library default (all zero fields)
     d = ow.select_config(None, dev(keys), 0, kb, vals)
     assert (d.block_threads, d.items_per_thread, d.rank_algorithm) == (0, 0, 0)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_fused_selection_matches_oracle_choice(ow, kb):
+    """The fused selection kernel (features + forward in one workgroup) picks
+    the oracle's best applicable class (up to near-ties within tolerance)."""
+    flat = random_params(40 + kb)
+    m = ow.Model(max_batch=1)
+    m.set_params(flat)
+    masks = [m.class_config(c)[1] for c in range(ow.MODEL_CLASSES)]
+    for n, dist, begin, end, vals in ((1000, "uniform", 0, kb, False),
+                                      (300_001, "zipf", 0, kb, True),
+                                      (1 << 20, "and2", 5, kb - 3, False)):
+        keys = W.make_keys(dist, 60 + n % 11, n, kb)
+        cfg = m.select_config(dev(keys), begin, end, vals)
+        want = M.forward(M.unflatten(flat.astype(np.float64)),
+                         M.features(keys, begin, end, vals)[None, :])["out"][0]
+        allowed = [c for c in range(ow.MODEL_CLASSES) if masks[c] & (1 if kb == 32 else 2)]
+        best = min(allowed, key=lambda c: want[c])
+        got = [c for c in allowed
+               if (m.class_config(c)[0].block_threads, m.class_config(c)[0].items_per_thread,
+                   m.class_config(c)[0].rank_algorithm) ==
+               (cfg.block_threads, cfg.items_per_thread, cfg.rank_algorithm)]
+        assert got, (n, dist)
+        assert best in got or min(abs(want[g] - want[best]) for g in got) <= \
+            RTOL * np.abs(want).max(), (n, dist, got, best)
+
+
+def test_committed_model_loads_and_picks_applicable_configs(ow):
+    from paper_2206_01784_amd import learned
+    m = ow.Model(max_batch=1, path=learned.DEFAULT_MODEL)
+    for kb in (32, 64):
+        for n in (1 << 17, 3_000_000):
+            keys = W.uniform(70 + n % 5, n, kb)
+            cfg = m.select_config(dev(keys), 0, kb, False)
+            assert ow.tile_items(kb, False, cfg) > 0
+            out = ow.sort_keys(dev(keys), config=cfg)
+            assert np.array_equal(out.cpu().numpy(), np.sort(keys))
