@@ -282,16 +282,63 @@ def run_segments(args):
     if int(temp[:4].cpu().numpy().view(np.uint32)[0]) != 0:
         log("[bench] ERROR: offsets reported invalid")
         sys.exit(1)
-    # spot check: a few segments against the oracle
-    import oracle
+    # spot check of a few segments by properties that fix a stable sort: the
+    # keys are ascending, the values (indices within the segment) are a
+    # permutation that maps each output key to its input, and equal keys
+    # keep increasing indices (full checks live in tests/)
     out_k, out_v = d_kout.cpu().numpy(), d_vout.cpu().numpy()
     for s_ in (0, S // 2, int(np.argmax(lengths)), S - 1):
         a, b = int(off[s_]), int(off[s_ + 1])
-        wk, wv = oracle.sort_segments(keys[a:b], np.array([0, b - a]), vals[a:b])
-        if not (np.array_equal(out_k[a:b], wk) and np.array_equal(out_v[a:b], wv)):
-            log(f"[bench] ERROR: segment {s_} differs from the oracle")
+        k_, v_ = out_k[a:b].astype(np.int64), out_v[a:b].astype(np.int64)
+        ok = (np.all(k_[1:] >= k_[:-1]) and np.array_equal(np.sort(v_), np.arange(b - a))
+              and np.array_equal(keys[a:b][v_], out_k[a:b])
+              and np.all((k_[1:] > k_[:-1]) | (v_[1:] > v_[:-1])))
+        if not ok:
+            log(f"[bench] ERROR: segment {s_} is not a stable sort of its input")
             sys.exit(1)
 
+    baselines = None
+    if not args.no_loop_baseline:
+        baselines = loop_baselines(args, ow, off, lengths, n, S, d_keys, d_vals, d_kout, d_vout,
+                                   stream, cap, ms_per_step)
+    bins = per_kind_summary(per_kind, ow, lengths, args.segment_limits)
+    dom_kind, dom_us, dom_launches = bins["dominant"]
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GKeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched stable sort of {S} segments (log-normal lengths, median 2000, "
+                        f"sigma 1.5, scaled to 2^{log2n} uint32 key/value pairs), one graph replay",
+            "n": n, "segments": S, "key_bits": 32, "values": True,
+            "segment_limits": list(args.segment_limits),
+            "tile": ow.tile_items(32, True, cfg, n),
+        },
+        "baselines": baselines,
+        "kernels_us": bins["table"],
+        "roofline": bins["roofline"] if dom_kind is not None else None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline_segments(keys, vals, off)
+    print(json.dumps(result), flush=True)
+
+
+def loop_baselines(args, ow, off, lengths, n, S, d_keys, d_vals, d_kout, d_vout, stream, cap,
+                   ms_per_step):
+    """The per-segment loop of plain pair sorts, eager and graph-captured."""
+    import torch
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     # Baseline 1: a loop of plain pair sorts, one per segment, eager.
     seg_temp = torch.empty(ow.sort_temp_bytes(int(lengths.max()), 32, True), dtype=torch.uint8,
                            device="cuda")
@@ -345,48 +392,15 @@ def run_segments(args):
         f"eager {sample_eager_ms:.2f} ms, graph {sample_graph_ms:.2f} ms; graph scaled to all "
         f"keys {loop_graph_ms:.1f} ms")
     del g2
-
-    bins = per_kind_summary(per_kind, ow, lengths, args.segment_limits)
-    dom_kind, dom_us, dom_launches = bins["dominant"]
-    result = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "GKeys/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"batched stable sort of {S} segments (log-normal lengths, median 2000, "
-                        f"sigma 1.5, scaled to 2^{log2n} uint32 key/value pairs), one graph replay",
-            "n": n, "segments": S, "key_bits": 32, "values": True,
-            "segment_limits": list(args.segment_limits),
-            "tile": ow.tile_items(32, True, cfg),
-        },
-        "baselines": {
-            "per_segment_loop_ms": round(loop_gpu_ms, 2),
-            "per_segment_loop_wall_ms": round(loop_ms, 2),
-            "per_segment_loop_graph_ms_scaled": round(loop_graph_ms, 2),
-            "per_segment_loop_graph_sample": f"first {len(sample)} segments, {sample_keys} pairs, "
-                                             f"{sample_graph_ms:.2f} ms",
-            "speedup_vs_loop": round(loop_gpu_ms / ms_per_step, 1),
-            "speedup_vs_loop_graph": round(loop_graph_ms / ms_per_step, 1),
-        },
-        "kernels_us": bins["table"],
-        "roofline": None,
-        "cpu_baseline": None,
+    return {
+        "per_segment_loop_ms": round(loop_gpu_ms, 2),
+        "per_segment_loop_wall_ms": round(loop_ms, 2),
+        "per_segment_loop_graph_ms_scaled": round(loop_graph_ms, 2),
+        "per_segment_loop_graph_sample": f"first {len(sample)} segments, {sample_keys} pairs, "
+                                         f"{sample_graph_ms:.2f} ms",
+        "speedup_vs_loop": round(loop_gpu_ms / ms_per_step, 1),
+        "speedup_vs_loop_graph": round(loop_graph_ms / ms_per_step, 1),
     }
-    if dom_kind is not None:
-        result["roofline"] = bins["roofline"]
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline_segments(keys, vals, off)
-    print(json.dumps(result), flush=True)
 
 
 SEGMENT_CLASS_CAPACITY = (512, 2048, 8192)
@@ -455,6 +469,8 @@ def main():
     ap.add_argument("--workload", default="u32_keys_uniform",
                     choices=sorted(WORKLOADS) + sorted(SEGMENT_WORKLOADS))
     ap.add_argument("--segment-limits", type=int, nargs=3, default=(0, 0, 0))
+    ap.add_argument("--no-loop-baseline", action="store_true",
+                    help="segmented workload: skip the per-segment loop baselines")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--hist-blocks-per-cu", type=int, default=0)
@@ -600,7 +616,7 @@ def main():
                         f"{'(key, uint32 value) pairs' if has_vals else 'keys (keys only)'}, "
                         f"8-bit digits, {places} binning passes",
             "n": n, "key_bits": key_bits, "values": has_vals, "distribution": dist,
-            "tile": ow.tile_items(key_bits, has_vals, cfg_plain),
+            "tile": ow.tile_items(key_bits, has_vals, cfg_plain, n),
             "hbm_fraction_whole_sort": round(whole_gbs / HBM_PEAK_GBS, 4),
         },
         "roofline": {

@@ -88,8 +88,10 @@ typedef struct {
 } onesweep_trace_t;
 
 /*
- * Kernel configuration. A NULL config, or 0 in a field, selects the default
- * for the key width and the presence of values. block_threads x
+ * Kernel configuration. A NULL config, or 0 in a field, selects the default:
+ * the autotuned plain configuration, a table of the fastest tile shape per
+ * key width, value presence and input size measured on MI355X over sizes
+ * 2^17..2^28 (smaller tiles below 2^18-2^19 keys). block_threads x
  * items_per_thread is the binning tile size T (Section 3 dispatches one
  * workgroup per tile). Only combinations compiled into the library are
  * accepted; others return ONESWEEP_ERROR_UNSUPPORTED.
@@ -313,9 +315,9 @@ onesweep_status_t onesweep_select_config(const onesweep_model_t *model, const vo
                                          onesweep_stream_t stream);
 
 /* Binning tile size T = block_threads x items_per_thread that `cfg` resolves
- * to for this key width and value presence; 0 if the config is unsupported.
- * Pure host computation. */
-size_t onesweep_tile_items(int key_bits, int has_values, const onesweep_config_t *cfg);
+ * to for this key width, value presence and n; 0 if the config is
+ * unsupported. Pure host computation. */
+size_t onesweep_tile_items(int key_bits, int has_values, size_t n, const onesweep_config_t *cfg);
 
 /* Message describing the calling thread's last failure ("" if none). */
 const char *onesweep_last_error(void);

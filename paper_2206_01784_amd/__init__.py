@@ -65,7 +65,7 @@ _lib.onesweep_sort_segments.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _vp,
 _lib.onesweep_tune_segments.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _i32, _i32,
                                         _i32, _i32, _cfgp, _vp]
 _lib.onesweep_tune_segments.restype = _i32
-_lib.onesweep_tile_items.argtypes = [_i32, _i32, _cfgp]
+_lib.onesweep_tile_items.argtypes = [_i32, _i32, _sz, _cfgp]
 _lib.onesweep_tile_items.restype = _sz
 _lib.onesweep_last_error.restype = ctypes.c_char_p
 _lib.onesweep_version.restype = ctypes.c_char_p
@@ -135,8 +135,10 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def tile_items(key_bits: int = 32, has_values: bool = False, config: Config | None = None) -> int:
-    return int(_lib.onesweep_tile_items(key_bits, int(has_values), _cfg_ptr(config)))
+def tile_items(key_bits: int = 32, has_values: bool = False, config: Config | None = None,
+               n: int = 1 << 28) -> int:
+    """Binning tile size the config resolves to (the default depends on n)."""
+    return int(_lib.onesweep_tile_items(key_bits, int(has_values), n, _cfg_ptr(config)))
 
 
 def sort_temp_bytes(n: int, key_bits: int = 32, has_values: bool = False, begin_bit: int = 0,

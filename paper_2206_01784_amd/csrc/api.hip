@@ -71,9 +71,9 @@ struct Resolved {
   onesweep_trace_t *trace;
 };
 
-onesweep_status_t resolve(int key_bits, bool has_values, const onesweep_config_t *cfg,
+onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const onesweep_config_t *cfg,
                           Resolved *r, bool segmented = false) {
-  r->shape = binning_default_shape(key_bits, has_values);
+  r->shape = binning_default_shape(key_bits, has_values, n);
   r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
   r->trace = nullptr;
   if (cfg != nullptr) {
@@ -191,7 +191,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
   onesweep_status_t st = check_common(temp_bytes, n, key_bits, begin_bit, end_bit);
   if (st) return st;
   Resolved rc;
-  if ((st = resolve(key_bits, has_values, cfg, &rc))) return st;
+  if ((st = resolve(key_bits, has_values, n, cfg, &rc))) return st;
   const int places = num_places(begin_bit, end_bit);
   const size_t tile = static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
   const SortLayout L = sort_layout(n, key_bits, has_values, places, tile);
@@ -412,7 +412,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   if (num_segments == 0 && n != 0)
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "%zu keys but no segment", n);
   Resolved rc;
-  if ((st = resolve(key_bits, has_values, cfg, &rc, true))) return st;
+  if ((st = resolve(key_bits, has_values, n, cfg, &rc, true))) return st;
   uint32_t limit[kSegClasses];
   if ((st = segment_limits(cfg, limit))) return st;
   const int places = num_places(begin_bit, end_bit);
@@ -660,7 +660,7 @@ onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits,
   onesweep_status_t st = check_common(&dummy, n, key_bits, begin_bit, end_bit);
   if (st) return st;
   Resolved rc;
-  if ((st = resolve(key_bits, false, cfg, &rc))) return st;
+  if ((st = resolve(key_bits, false, n, cfg, &rc))) return st;
   const int places = num_places(begin_bit, end_bit);
   if (places == 0) return ONESWEEP_SUCCESS;
   if (!d_hist) return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_hist is NULL");
@@ -701,7 +701,7 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
   const bool has_values = d_src_vals != nullptr || d_dst_vals != nullptr;
   Resolved rc;
   onesweep_status_t st;
-  if ((st = resolve(key_bits, has_values, cfg, &rc))) return st;
+  if ((st = resolve(key_bits, has_values, n, cfg, &rc))) return st;
   const size_t tile = static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
   const uint32_t tiles = static_cast<uint32_t>((n + tile - 1) / tile);
   const size_t need = kAlign + align_up(sizeof(uint32_t) * kRadix * static_cast<size_t>(tiles));
@@ -885,10 +885,10 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
                                 cfg_out, stream);
 }
 
-size_t onesweep_tile_items(int key_bits, int has_values, const onesweep_config_t *cfg) {
+size_t onesweep_tile_items(int key_bits, int has_values, size_t n, const onesweep_config_t *cfg) {
   if (key_bits != 32 && key_bits != 64) return 0;
   Resolved rc;
-  if (resolve(key_bits, has_values != 0, cfg, &rc) != ONESWEEP_SUCCESS) return 0;
+  if (resolve(key_bits, has_values != 0, n, cfg, &rc) != ONESWEEP_SUCCESS) return 0;
   return static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
 }
 

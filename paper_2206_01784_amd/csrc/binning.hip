@@ -429,6 +429,10 @@ __global__ void __launch_bounds__(kBlock)
 
 // Shapes also built for the large segments of a segmented sort.
 #define ONESWEEP_SEGMENT_BINNING_SHAPES(X) \
+  X(uint32_t, false, 256, 8, 0)            \
+  X(uint32_t, true, 256, 8, 0)             \
+  X(uint64_t, false, 256, 8, 0)            \
+  X(uint64_t, true, 256, 8, 0)             \
   X(uint32_t, false, 256, 16, 0)           \
   X(uint32_t, false, 512, 16, 0)           \
   X(uint32_t, false, 1024, 8, 0)           \
@@ -457,11 +461,21 @@ bool binning_shape_supported(const BinningShape &s, bool segmented) {
   return false;
 }
 
-BinningShape binning_default_shape(int key_bits, bool has_values) {
-  // Measured on MI355X (2^28 uint32 keys / pairs, 2^27 uint64 pairs).
-  if (key_bits == 64) return BinningShape{64, has_values, 1024, 8, kRankBallot};
-  if (has_values) return BinningShape{32, true, 512, 16, kRankBallot};
-  return BinningShape{32, false, 1024, 8, kRankBallot};
+// The autotuned plain configuration: the fastest tile shape per key width,
+// value presence and input size, from 1000 timing records of every built
+// shape over the seeded sweep of sizes 2^17..2^28 on MI355X (plus the
+// full-size benchmarks for 2^27 and more). Small inputs want more, smaller
+// tiles to fill 256 CUs; from 2^18-2^19 keys on, 1024 x 8 wins except for
+// 32-bit pairs at 2^27 and more, where 512 x 16 is as fast or faster.
+BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
+  if (key_bits == 64) {
+    if (has_values && n < (size_t(3) << 16)) return BinningShape{64, true, 256, 8, kRankBallot};
+    if (n < (size_t(1) << 19)) return BinningShape{64, has_values, 512, 8, kRankBallot};
+    return BinningShape{64, has_values, 1024, 8, kRankBallot};
+  }
+  if (n < (size_t(1) << 18)) return BinningShape{32, has_values, 256, 8, kRankBallot};
+  if (has_values && n >= (size_t(1) << 27)) return BinningShape{32, true, 512, 16, kRankBallot};
+  return BinningShape{32, has_values, 1024, 8, kRankBallot};
 }
 
 hipError_t launch_binning(const BinningShape &s, bool segmented, const void *args,

@@ -31,7 +31,7 @@ struct BinningShape {
 // `segmented`: the variant whose tiles are those of a segmented sort's large
 // segments (BinningArgs::seg); fewer shapes are built for it.
 bool binning_shape_supported(const BinningShape &s, bool segmented);
-BinningShape binning_default_shape(int key_bits, bool has_values);
+BinningShape binning_default_shape(int key_bits, bool has_values, size_t n);
 
 // `args` points to BinningArgs<uint32_t> or BinningArgs<uint64_t>.
 hipError_t launch_binning(const BinningShape &s, bool segmented, const void *args,

@@ -71,7 +71,7 @@ onesweep_status_t check_shape_of(const ModelClass &c) {
     cfg.rank_algorithm = c.rank_algorithm;
     cfg.hist_blocks_per_cu = c.hist_blocks_per_cu;
     for (int v = 0; v < 2; ++v)
-      if (onesweep_tile_items(kb, v, &cfg) == 0)
+      if (onesweep_tile_items(kb, v, size_t(1) << 28, &cfg) == 0)
         return fail(ONESWEEP_ERROR_UNSUPPORTED, "model class %d x %d (rank %d) not built for %d-bit keys",
                     c.block_threads, c.items_per_thread, c.rank_algorithm, kb);
   }

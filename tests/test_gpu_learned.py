@@ -252,3 +252,47 @@ def test_committed_model_loads_and_picks_applicable_configs(ow):
             assert ow.tile_items(kb, False, cfg) > 0
             out = ow.sort_keys(dev(keys), config=cfg)
             assert np.array_equal(out.cpu().numpy(), np.sort(keys))
+
+
+def test_trained_model_gains_over_the_fixed_default(ow):
+    """What the trained network gains over the method without it: on small
+    inputs, where one fixed tile shape (the 2^28 benchmarks' choice) is
+    slow, the model's pick sorts faster, bit-exactly. Sort time only; the
+    selection itself (one launch and a synchronisation) is reported by the
+    sweep evaluation, not asserted here."""
+    from paper_2206_01784_amd import learned
+    m = ow.Model(max_batch=1, path=learned.DEFAULT_MODEL)
+    cases = [(32, True, 1 << 17, (512, 16)), (64, False, 1 << 17, (1024, 8)),
+             (64, True, 1 << 17, (1024, 8))]
+    gains = []
+    for kb, vals, n, fixed in cases:
+        keys = dev(W.uniform(80 + kb, n, kb))
+        v = torch.arange(n, dtype=torch.int32, device="cuda").view(torch.uint32)
+        pick = m.select_config(keys, 0, kb, vals)
+        fixed_cfg = ow.make_config(block_threads=fixed[0], items_per_thread=fixed[1])
+        temp = torch.empty(max(ow.sort_temp_bytes(n, kb, vals, config=c)
+                               for c in (pick, fixed_cfg)), dtype=torch.uint8, device="cuda")
+        out, vout = torch.empty_like(keys), torch.empty_like(v)
+
+        def timed(cfg, reps=200):
+            def run():
+                if vals:
+                    ow.sort_pairs(keys, v, keys_out=out, values_out=vout, temp=temp, config=cfg)
+                else:
+                    ow.sort_keys(keys, out=out, temp=temp, config=cfg)
+            run()
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            for _ in range(reps):
+                run()
+            e.record()
+            torch.cuda.synchronize()
+            return s.elapsed_time(e) / reps
+        t_fixed = min(timed(fixed_cfg) for _ in range(3))
+        t_pick = min(timed(pick) for _ in range(3))
+        gains.append(t_fixed / t_pick)
+        want = np.sort(keys.cpu().numpy())
+        assert np.array_equal(out.cpu().numpy(), want)
+        print(f"kb={kb} vals={vals} n={n}: fixed {t_fixed * 1e3:.1f} us, pick "
+              f"({pick.block_threads}x{pick.items_per_thread}) {t_pick * 1e3:.1f} us")
+    assert float(np.exp(np.mean(np.log(gains)))) > 1.0, gains

@@ -104,8 +104,9 @@ LIMITS = [(0, 0, 0), (-1, -1, -1), (-1, -1, 0), (100, 1000, 5000), (512, -1, 819
 
 
 @pytest.mark.parametrize("limits", LIMITS)
-@pytest.mark.parametrize("kb,shape", [(32, (256, 16)), (32, (512, 16)), (32, (1024, 8)),
-                                      (64, (512, 8)), (64, (256, 16))])
+@pytest.mark.parametrize("kb,shape", [(32, (256, 8)), (32, (256, 16)), (32, (512, 16)),
+                                      (32, (1024, 8)), (64, (256, 8)), (64, (512, 8)),
+                                      (64, (256, 16))])
 def test_segments_class_limits_and_tiles(ow, limits, kb, shape):
     cfg = ow.make_config(block_threads=shape[0], items_per_thread=shape[1],
                          segment_limits=limits)
