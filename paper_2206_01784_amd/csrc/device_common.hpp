@@ -118,7 +118,24 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
 }
 
 // Inclusive sum over the lanes of a wavefront.
+#ifndef ONESWEEP_DPP_SCAN
+#define ONESWEEP_DPP_SCAN 1
+#endif
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+#if ONESWEEP_DPP_SCAN
+  // Data-parallel primitives: within each row of 16 lanes add the values
+  // 1, 2, 4 and 8 lanes back (lanes whose source lies outside the row add
+  // 0), then broadcast the last lane of rows 0 and 2 into rows 1 and 3 and
+  // the last lane of row 1 into rows 2 and 3. No LDS traffic.
+  constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+  v += __builtin_amdgcn_update_dpp(0u, v, kRowShr | 1, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, kRowShr | 2, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, kRowShr | 4, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, kRowShr | 8, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, kRowBcast15, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, kRowBcast31, 0xc, 0xf, false);
+  return v;
+#else
   const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
@@ -126,6 +143,7 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
     if (lane >= off) v += t;
   }
   return v;
+#endif
 }
 
 // In-place exclusive scan of a table of per-wave digit counts,

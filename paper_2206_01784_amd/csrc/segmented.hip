@@ -288,6 +288,15 @@ constexpr int lds_sort_waves_per_eu() {
   return kBlock >= 1024 && sizeof(K) == 4 ? 8 : 4;
 }
 
+// Wave-level digit match of the LDS sort: one ballot per digit bit, or
+// 64-bit presence masks in LDS (an atomic OR per lane and one read per
+// batch: far fewer vector instructions, which is what bounds this kernel).
+// The masks overlay the tile buffer, which is idle while keys are ranked.
+#ifndef ONESWEEP_LDS_PRESENCE
+#define ONESWEEP_LDS_PRESENCE 1
+#endif
+constexpr bool kLdsPresence = ONESWEEP_LDS_PRESENCE != 0;
+
 template <typename K, bool kVals, int kBlock, int kIpt>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(lds_sort_waves_per_eu<K, kBlock>())))
@@ -301,6 +310,16 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ uint32_t s_wave_sum[kWaves];
   K *s_keys = reinterpret_cast<K *>(s_data);
   uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_data);
+  uint64_t *s_mask = reinterpret_cast<uint64_t *>(s_data);  // [wave][digit] while ranking
+  static_assert(!kLdsPresence || kDataBytes >= sizeof(uint64_t) * kWaves * kRadix,
+                "presence masks fit the tile buffer");
+  auto clear_masks = [&]() {
+    if constexpr (kLdsPresence) {
+      uint4 *z = reinterpret_cast<uint4 *>(s_data);
+      for (int x = threadIdx.x; x < kWaves * kRadix / 2; x += kBlock)
+        z[x] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -312,6 +331,7 @@ __global__ void __launch_bounds__(kBlock)
   const uint32_t wave_first = static_cast<uint32_t>(wave) * kWaveItems;
 
   for (int x = tid; x < kWaves * kRadix; x += kBlock) s_cnt[x] = 0u;
+  clear_masks();
   __syncthreads();
 
   for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
@@ -337,18 +357,29 @@ __global__ void __launch_bounds__(kBlock)
         if (wave_first + i * kWave < len) {
           const uint32_t d = digit_of(key[i], shift, mask);
           uint32_t peers_lo = ~0u, peers_hi = ~0u;
+          uint64_t *m = &s_mask[wave * kRadix + d];
+          if constexpr (kLdsPresence) {
+            __hip_atomic_fetch_or(m, 1ull << lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t peers = *m;
+            peers_lo = static_cast<uint32_t>(peers);
+            peers_hi = static_cast<uint32_t>(peers >> 32);
+          } else {
 #pragma unroll
-          for (int b = 0; b < kRadixBits; ++b) {
-            const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);
-            const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
-            peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
-            peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
+            for (int b = 0; b < kRadixBits; ++b) {
+              const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);
+              const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
+              peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
+              peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
+            }
           }
           uint32_t &c = s_cnt[wave * kRadix + d];
           const uint32_t prior = c;
           pos[i] = prior + __builtin_amdgcn_mbcnt_hi(peers_hi,
                                                      __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
           c = prior + static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi));
+          // every lane of the group writes the same values
+          if constexpr (kLdsPresence) *m = 0ull;
           __builtin_amdgcn_wave_barrier();
         }
       }
@@ -376,8 +407,12 @@ __global__ void __launch_bounds__(kBlock)
         for (int i = 0; i < kIpt; ++i)
           if (wave_first + i * kWave < len) val[i] = s_vals[wave_first + i * kWave + lane];
       }
-      // The counters were last read before the scatter's barrier.
+      // The counters were last read before the scatter's barrier; the masks
+      // overlay the tile buffer, so they are cleared once every thread has
+      // read its keys (and values) back.
+      if constexpr (kLdsPresence) __syncthreads();
       for (int x = tid; x < kWaves * kRadix; x += kBlock) s_cnt[x] = 0u;
+      clear_masks();
       __syncthreads();
     }
 #pragma unroll
