@@ -229,7 +229,8 @@ def run_segments(args):
     d_kout = torch.empty_like(d_keys)
     d_vout = torch.empty_like(d_vals)
     cfg = ow.make_config(args.block, args.ipt, rank_algorithm=args.rank,
-                         segment_limits=tuple(args.segment_limits))
+                         segment_limits=tuple(args.segment_limits),
+                         segment_streams=args.segment_streams)
     temp = torch.empty(ow.sort_segments_temp_bytes(n, S, 32, True, config=cfg),
                        dtype=torch.uint8, device="cuda")
 
@@ -321,6 +322,7 @@ def run_segments(args):
                         f"sigma 1.5, scaled to 2^{log2n} uint32 key/value pairs), one graph replay",
             "n": n, "segments": S, "key_bits": 32, "values": True,
             "segment_limits": list(args.segment_limits),
+            "segment_streams": 1 if args.segment_streams == 1 else 2,
             "tile": ow.tile_items(32, True, cfg, n),
         },
         "baselines": baselines,
@@ -469,6 +471,8 @@ def main():
     ap.add_argument("--workload", default="u32_keys_uniform",
                     choices=sorted(WORKLOADS) + sorted(SEGMENT_WORKLOADS))
     ap.add_argument("--segment-limits", type=int, nargs=3, default=(0, 0, 0))
+    ap.add_argument("--segment-streams", type=int, default=0,
+                    help="segmented workload: 0 two streams (default), 1 one stream")
     ap.add_argument("--no-loop-baseline", action="store_true",
                     help="segmented workload: skip the per-segment loop baselines")
     ap.add_argument("--block", type=int, default=0)

@@ -109,6 +109,9 @@ typedef struct {
                                 the class's capacity (512, 2048, 8192 keys), -1 =
                                 class unused. Longer segments are binned tile by
                                 tile. */
+    int segment_streams;     /* segmented sort only: 0 = two streams when a batch has
+                                both LDS-sorted and tiled segments (see
+                                onesweep_sort_segments), 1 = the caller's stream only */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 
@@ -187,7 +190,15 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
  *    items_per_thread pick the binning tile of the longer segments (a
  *    subset of the shapes of onesweep_sort_pairs is built for it).
  * The enqueued sequence is a fixed list of kernels whatever the offsets, so
- * it can be captured once and replayed.
+ * it can be captured once and replayed. When the batch can hold both
+ * LDS-sorted and tiled segments (and no trace is requested), the LDS-sort
+ * kernels run on a library-owned second stream, forked from and joined back
+ * to `stream` with events, so they overlap the tiled segments' passes. That
+ * stream and its two events are created once per device, on the first such
+ * call made outside graph capture (calls inside a capture before then use
+ * one stream), and live until the process ends. Concurrent calls on one
+ * device share the second stream; while one call is being captured, no other
+ * thread may issue a segmented sort on that device until the capture ends.
  */
 onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
                                          const void *d_keys_in, void *d_keys_out,

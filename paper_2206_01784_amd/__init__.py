@@ -47,7 +47,7 @@ class Config(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_int), ("block_threads", ctypes.c_int),
                 ("items_per_thread", ctypes.c_int), ("hist_blocks_per_cu", ctypes.c_int),
                 ("rank_algorithm", ctypes.c_int), ("segment_limits", ctypes.c_int * 3),
-                ("trace", ctypes.POINTER(Trace))]
+                ("segment_streams", ctypes.c_int), ("trace", ctypes.POINTER(Trace))]
 
 
 _vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
@@ -99,9 +99,9 @@ RANK_DEFAULT, RANK_BALLOT, RANK_PRESENCE, RANK_ATOMIC = 0, 1, 2, 3
 
 def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,
                 digit_bits: int = 0, rank_algorithm: int = 0, segment_limits=(0, 0, 0),
-                trace: Trace | None = None) -> Config:
+                segment_streams: int = 0, trace: Trace | None = None) -> Config:
     c = Config(digit_bits, block_threads, items_per_thread, hist_blocks_per_cu, rank_algorithm,
-               (ctypes.c_int * 3)(*segment_limits), None)
+               (ctypes.c_int * 3)(*segment_limits), segment_streams, None)
     if trace is not None:
         c.trace = ctypes.pointer(trace)
     return c

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -317,6 +318,9 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
 // lengths in (limit[c - 1], limit[c]]; an unused class repeats the previous
 // limit.
 onesweep_status_t segment_limits(const onesweep_config_t *cfg, uint32_t limit[kSegClasses]) {
+  if (cfg && (cfg->segment_streams < 0 || cfg->segment_streams > 1))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "segment_streams %d not 0 or 1",
+                cfg->segment_streams);
   uint32_t prev = 0;
   for (int c = 0; c < kSegClasses; ++c) {
     const int cap = lds_class_capacity(c);
@@ -396,6 +400,44 @@ onesweep_status_t lds_blocks_per_cu(int key_bits, bool has_values, int cls, int 
   if (b <= 0) b = 1;
   if (slot) slot->store(b, std::memory_order_relaxed);
   *blocks = b;
+  return ONESWEEP_SUCCESS;
+}
+
+// The segmented sort's second stream: after classify, the LDS-sort classes
+// run on it while the large segments are binned on the caller's stream (the
+// two touch disjoint key ranges), joined back through an event. One stream
+// and two events per device, created on first use outside graph capture and
+// kept for the life of the process; the lock serialises the enqueue of the
+// fork/join pair across host threads.
+struct SegmentStreams {
+  std::mutex lock;
+  bool ready = false;
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+SegmentStreams g_segment_streams[64];
+
+onesweep_status_t segment_streams(hipStream_t stream, SegmentStreams **out,
+                                  std::unique_lock<std::mutex> *hold) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return ONESWEEP_SUCCESS;
+  SegmentStreams &r = g_segment_streams[dev];
+  std::unique_lock<std::mutex> lk(r.lock);
+  if (!r.ready) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return ONESWEEP_SUCCESS;  // cannot create resources while capturing: one stream
+    e = hipStreamCreateWithFlags(&r.aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r.join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "segmented sort stream setup");
+    r.ready = true;
+  }
+  *hold = std::move(lk);
+  *out = &r;
   return ONESWEEP_SUCCESS;
 }
 
@@ -511,10 +553,27 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   ca.plan = plan;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_CLASSIFY, "classify", launch_classify(ca, stream));
 
+  // Both halves present and no per-launch tracing: fork the LDS classes
+  // onto the second stream, at half their occupancy so that binning
+  // workgroups share the CUs with them.
+  bool any_lds = false;
+  for (int c = 0; c < kSegClasses; ++c) any_lds = any_lds || L.capacity[c] > 0;
+  SegmentStreams *ss = nullptr;
+  std::unique_lock<std::mutex> hold;
+  if (any_lds && L.max_large > 0 && !rc.trace && !(cfg && cfg->segment_streams == 1))
+    if ((st = segment_streams(stream, &ss, &hold))) return st;
+  hipStream_t lds_stream = stream;
+  if (ss) {
+    hipError_t e = hipEventRecord(ss->fork, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ss->aux, ss->fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "segmented sort fork");
+    lds_stream = ss->aux;
+  }
   for (int c = 0; c < kSegClasses; ++c) {
     if (L.capacity[c] == 0) continue;
     int per_cu = 0;
     if ((st = lds_blocks_per_cu(key_bits, has_values, c, &per_cu))) return st;
+    if (ss) per_cu = std::max(1, per_cu / 2);
     LdsSortArgs la{};
     la.keys_in = keys_in;
     la.keys_out = keys_out;
@@ -530,7 +589,11 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
     const uint32_t grid =
         std::min<uint32_t>(L.capacity[c], static_cast<uint32_t>(cus) * static_cast<uint32_t>(per_cu));
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_LDS_SORT, "lds sort",
-                    launch_lds_sort(key_bits, has_values, la, grid, stream));
+                    launch_lds_sort(key_bits, has_values, la, grid, lds_stream));
+  }
+  if (ss) {
+    hipError_t e = hipEventRecord(ss->join, ss->aux);
+    if (e != hipSuccess) return hip_fail(e, "segmented sort join");
   }
   if (L.max_large == 0) return ONESWEEP_SUCCESS;
 
@@ -622,6 +685,10 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
     pa.key_bytes = static_cast<int>(kb);
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_COPY, "segment copy",
                     launch_segment_copy(pa, std::min(L.max_tiles, stream_grid), stream));
+  }
+  if (ss) {
+    hipError_t e = hipStreamWaitEvent(stream, ss->join, 0);
+    if (e != hipSuccess) return hip_fail(e, "segmented sort join");
   }
   return ONESWEEP_SUCCESS;
 }

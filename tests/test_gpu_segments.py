@@ -103,6 +103,24 @@ LIMITS = [(0, 0, 0), (-1, -1, -1), (-1, -1, 0), (100, 1000, 5000), (512, -1, 819
           (1, 2, 3)]
 
 
+@pytest.mark.parametrize("kb", [32, 64])
+def test_segments_one_stream_and_two_streams_agree(ow, kb):
+    """The LDS classes on the second stream (default) and everything on the
+    caller's stream give the same, oracle-exact result."""
+    off = edge_offsets(reps=3, seed=kb)
+    n = int(off[-1])
+    keys = keys_for(kb, n, 12)
+    vals = np.arange(n, dtype=np.uint32)
+    check(ow, keys, off, vals, config=ow.make_config(segment_streams=1), what="one stream")
+    check(ow, keys, off, vals, config=ow.make_config(segment_streams=0), what="two streams")
+    # a non-default stream of the caller
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        got_k, got_v, _ = run(ow, keys, off, vals)
+    want_k, want_v = oracle.sort_segments(keys, off, vals)
+    assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v)
+
+
 @pytest.mark.parametrize("limits", LIMITS)
 @pytest.mark.parametrize("kb,shape", [(32, (256, 8)), (32, (256, 16)), (32, (512, 16)),
                                       (32, (1024, 8)), (64, (256, 8)), (64, (512, 8)),
