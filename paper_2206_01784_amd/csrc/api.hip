@@ -194,7 +194,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
   Resolved rc;
   if ((st = resolve(key_bits, has_values, n, cfg, &rc))) return st;
   const int places = num_places(begin_bit, end_bit);
-  const size_t tile = static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
+  const size_t tile = binning_tile_items(rc.shape);
   const SortLayout L = sort_layout(n, key_bits, has_values, places, tile);
   if (d_temp == nullptr) {
     *temp_bytes = L.total;
@@ -458,7 +458,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   uint32_t limit[kSegClasses];
   if ((st = segment_limits(cfg, limit))) return st;
   const int places = num_places(begin_bit, end_bit);
-  const size_t tile = static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
+  const size_t tile = binning_tile_items(rc.shape);
   const SegmentLayout L =
       segment_layout(n, num_segments, key_bits, has_values, places, tile, limit);
   if (d_temp == nullptr) {
@@ -769,7 +769,7 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
   Resolved rc;
   onesweep_status_t st;
   if ((st = resolve(key_bits, has_values, n, cfg, &rc))) return st;
-  const size_t tile = static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
+  const size_t tile = binning_tile_items(rc.shape);
   const uint32_t tiles = static_cast<uint32_t>((n + tile - 1) / tile);
   const size_t need = kAlign + align_up(sizeof(uint32_t) * kRadix * static_cast<size_t>(tiles));
   if (d_temp == nullptr) {
@@ -956,7 +956,7 @@ size_t onesweep_tile_items(int key_bits, int has_values, size_t n, const oneswee
   if (key_bits != 32 && key_bits != 64) return 0;
   Resolved rc;
   if (resolve(key_bits, has_values != 0, n, cfg, &rc) != ONESWEEP_SUCCESS) return 0;
-  return static_cast<size_t>(rc.shape.block) * rc.shape.ipt;
+  return binning_tile_items(rc.shape);
 }
 
 const char *onesweep_last_error(void) { return g_error; }

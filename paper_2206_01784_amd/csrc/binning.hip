@@ -467,6 +467,10 @@ bool binning_shape_supported(const BinningShape &s, bool segmented) {
 // full-size benchmarks for 2^27 and more). Small inputs want more, smaller
 // tiles to fill 256 CUs; from 2^18-2^19 keys on, 1024 x 8 wins except for
 // 32-bit pairs at 2^27 and more, where 512 x 16 is as fast or faster.
+size_t binning_tile_items(const BinningShape &s) {
+  return static_cast<size_t>(s.block) * static_cast<size_t>(s.ipt);
+}
+
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
   if (key_bits == 64) {
     if (has_values && n < (size_t(3) << 16)) return BinningShape{64, true, 256, 8, kRankBallot};

@@ -32,6 +32,8 @@ struct BinningShape {
 // segments (BinningArgs::seg); fewer shapes are built for it.
 bool binning_shape_supported(const BinningShape &s, bool segmented);
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n);
+// Keys per binning tile of a shape.
+size_t binning_tile_items(const BinningShape &s);
 
 // `args` points to BinningArgs<uint32_t> or BinningArgs<uint64_t>.
 hipError_t launch_binning(const BinningShape &s, bool segmented, const void *args,

@@ -126,7 +126,7 @@ def check_sort(ow, keys, vals, begin, end, cfg=None, inplace=False):
 def test_sort_every_shape_ragged_sizes(ow, kb, vals, rank):
     for block, ipt in SHAPES[(kb, vals)]:
         cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank)
-        T = block * ipt
+        T = ow.tile_items(kb, vals, cfg)
         for n in (2, T - 1, T + 1, 7 * T + 333):
             keys = W.uniform(7 + n % 13, n, kb)
             v = np.arange(n, dtype=np.uint32) if vals else None
