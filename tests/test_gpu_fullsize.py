@@ -78,3 +78,36 @@ def test_full_u64_pairs(ow):
     wk, wv = oracle.sort(keys, vals)
     assert np.array_equal(ko.cpu().numpy(), wk)
     assert np.array_equal(vo.cpu().numpy(), wv)
+
+
+def test_full_segments_lognormal_20000(ow):
+    """The batched workload at full size: 20,000 log-normal segments, 2^26
+    uint32 pairs (values = index within the segment), default class limits
+    and tiles, captured in a graph and replayed, checked against the
+    per-segment oracle element by element."""
+    lengths = W.lognormal_segment_lengths(num_segments=20000, total=1 << 26, seed=4)
+    off = W.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    keys = W.uniform(4, n)
+    seg_of = np.repeat(np.arange(20000), lengths)
+    vals = (np.arange(n, dtype=np.int64) - off[seg_of]).astype(np.uint32)
+    tk, tv = torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda()
+    to = torch.from_numpy(off.astype(np.uint32)).cuda()
+    ko, vo = torch.empty_like(tk), torch.empty_like(tv)
+    temp = torch.empty(ow.sort_segments_temp_bytes(n, 20000, 32, True), dtype=torch.uint8,
+                       device="cuda")
+    ow.sort_segments(tk, to, tv, keys_out=ko, values_out=vo, temp=temp)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ow.sort_segments(tk, to, tv, keys_out=ko, values_out=vo, temp=temp, stream=s)
+    ko.zero_()
+    vo.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    wk, wv = oracle.sort_segments(keys, off, vals)
+    assert np.array_equal(ko.cpu().numpy(), wk)
+    assert np.array_equal(vo.cpu().numpy(), wv)
