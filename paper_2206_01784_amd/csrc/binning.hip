@@ -94,6 +94,12 @@ __global__ void __launch_bounds__(kBlock)
   // in the wave (word 0) and, for kRankPresence, the 64-bit presence mask
   // (words 2-3). The region is reused for the regrouped tile afterwards.
   constexpr int kEntryWords = kRank == kRankPresence ? 4 : 1;
+  // One-digit tiles skip the LDS regrouping and write keys and values from
+  // registers. Built for 32-bit pairs only, where it is measured faster;
+  // keys-only tiles gain nothing from it (the pass waits on the look-back,
+  // not on LDS), and 64-bit pairs would spill holding their keys across the
+  // look-back.
+  constexpr bool kShortCircuit = sizeof(K) == 4 && kVals;
   constexpr size_t kKeyBytes = sizeof(K) * kTile;
   constexpr size_t kRankBytes = sizeof(uint32_t) * kWaves * kRadix * kEntryWords;
   constexpr size_t kStageBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
@@ -101,6 +107,7 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_wave_sum[kRadix / kWave];
   __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_uniform;  // 1 + the tile's only digit, or 0
 
   uint32_t *s_rank = reinterpret_cast<uint32_t *>(s_stage);
   K *s_keys = reinterpret_cast<K *>(s_stage);
@@ -125,7 +132,10 @@ __global__ void __launch_bounds__(kBlock)
     for (int i = tid; i < static_cast<int>(kRankBytes / 16); i += kBlock)
       z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
-  if (tid == 0) s_tile = atomicAdd(a.tile_counter, 1u);
+  if (tid == 0) {
+    s_tile = atomicAdd(a.tile_counter, 1u);
+    s_uniform = 0u;
+  }
   __syncthreads();
   const uint32_t tile = s_tile;
   uint32_t tile_base, tile_count, bin_base;
@@ -251,6 +261,8 @@ __global__ void __launch_bounds__(kBlock)
     }
     published = total;
     if (!full && static_cast<uint32_t>(tid) == mask) published -= kTile - tile_count;
+    if (kShortCircuit && full && total == static_cast<uint32_t>(kTile))
+      s_uniform = 1u + static_cast<uint32_t>(tid);
     // 4a. Publish this tile's count (a first tile's count is already its
     // prefix).
     store_status(&a.status[static_cast<size_t>(tile) * kRadix + tid],
@@ -275,10 +287,14 @@ __global__ void __launch_bounds__(kBlock)
   for (int i = 0; i < kIpt; ++i)
     pos[i] += s_rank[wave_table + digit_of(key[i], shift, mask) * kEntryWords];
   __syncthreads();  // the rank tables are dead; the region now holds the tile
+  const uint32_t uniform = kShortCircuit ? s_uniform : 0u;
 
-  // 5a. Regroup the keys by digit in LDS.
+  // 5a. Regroup the keys by digit in LDS (not needed when the tile has one
+  // digit: its sorted order is its input order).
+  if (uniform == 0u) {
 #pragma unroll
-  for (int i = 0; i < kIpt; ++i) s_keys[pos[i]] = key[i];
+    for (int i = 0; i < kIpt; ++i) s_keys[pos[i]] = key[i];
+  }
 
   uint32_t val[kVals ? kIpt : 1];
   if constexpr (kVals) {
@@ -333,6 +349,26 @@ __global__ void __launch_bounds__(kBlock)
     s_gbase[tid] = bin_start + exclusive - local_start;
   }
   __syncthreads();
+
+  // 5b'. Short-circuit: every key of a one-digit tile goes to its bin at its
+  // input position, straight from registers.
+  if (uniform != 0u) {
+    const uint32_t g0 = s_gbase[uniform - 1u] + static_cast<uint32_t>(wave * kWaveItems + lane);
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+      const uint32_t g = g0 + static_cast<uint32_t>(i * kWave);
+      if (!kCheckedStores || g < n) dst[g] = key[i];
+    }
+    if constexpr (kVals) {
+      uint32_t *__restrict__ vdst = a.vals[dst_id];
+#pragma unroll
+      for (int i = 0; i < kIpt; ++i) {
+        const uint32_t g = g0 + static_cast<uint32_t>(i * kWave);
+        if (!kCheckedStores || g < n) vdst[g] = val[i];
+      }
+    }
+    return;
+  }
 
   // 5b. Write runs of keys to their bins.
   uint32_t dst_idx[kVals ? kIpt : 1];

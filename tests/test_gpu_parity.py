@@ -145,6 +145,36 @@ def test_sort_distributions(ow, kb, dist):
         check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb, cfg)
 
 
+@pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
+@pytest.mark.parametrize("rank", RANKS)
+def test_one_digit_tiles(ow, kb, vals, rank):
+    """Tiles whose keys share the place's digit take the short-circuit write
+    (Section 3.3): runs of a tile's length and of other lengths, so tiles are
+    one-digit, mixed, or straddle two runs; the ragged last tile's real keys
+    all carry the padding digit (it must not short-circuit)."""
+    for block, ipt in SHAPES[(kb, vals)]:
+        cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank)
+        T = ow.tile_items(kb, vals, cfg)
+        for run in (T, 3 * T // 2, 4096):
+            n = 6 * T + 77
+            keys = W.runs(11 + run % 7, n, kb, run=run, low_bits=8, last_high_ones=True)
+            v = np.arange(n, dtype=np.uint32) if vals else None
+            check_sort(ow, keys, v, 0, kb, cfg)
+            # one pass at a high place: the final chained-scan state as well
+            shift, width = kb - 8, 8
+            hist = oracle.histograms(keys, shift, shift + width, width)[0]
+            off = oracle.exclusive_sums(hist[None, :])[0].astype(np.uint32)
+            dk, dv, temp = ow.binning_pass(dev(keys), dev(off), shift, width,
+                                           src_values=None if v is None else dev(v), config=cfg)
+            wk, wv = oracle.binning_pass(keys, shift, width, off, v)
+            assert np.array_equal(host(dk), wk), (block, ipt, run)
+            if vals:
+                assert np.array_equal(host(dv), wv), (block, ipt, run)
+            g = -(-n // T)
+            st = host(temp[256:256 + g * 256 * 4].view(torch.uint32)).reshape(g, 256)
+            assert np.array_equal(st, oracle.pass_status(keys, shift, width, T))
+
+
 @pytest.mark.parametrize("kb", [32, 64])
 def test_sort_partial_bit_ranges(ow, kb):
     n = 123457

@@ -146,6 +146,23 @@ def test_segments_distributions(ow, kb, dist):
 
 
 @pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("with_vals", [False, True])
+def test_segments_one_digit_tiles(ow, kb, with_vals):
+    """Large segments whose tiles share their high digits (runs of 4096 and
+    8192 keys) take the short-circuit write; the last run has every high bit
+    set, the digit of the padding lanes."""
+    off = edge_offsets(reps=2, seed=21)
+    n = int(off[-1])
+    vals = np.arange(n, dtype=np.uint32) if with_vals else None
+    for run_len in (4096, 8192):
+        keys = W.runs(23, n, kb, run=run_len, low_bits=8, last_high_ones=True)
+        for shape in ((256, 16), (1024, 8)):
+            cfg = ow.make_config(block_threads=shape[0], items_per_thread=shape[1],
+                                 segment_limits=(-1, -1, -1))
+            check(ow, keys, off, vals, config=cfg, what=(run_len, shape))
+
+
+@pytest.mark.parametrize("kb", [32, 64])
 @pytest.mark.parametrize("in_place", [False, True])
 def test_segments_partial_bit_ranges(ow, kb, in_place):
     off = edge_offsets(reps=1, seed=3)

@@ -180,6 +180,22 @@ def distinct16(seed: int, n: int, key_bits: int = 32) -> np.ndarray:
     return table[idx]
 
 
+def runs(seed: int, n: int, key_bits: int = 32, run: int = 1 << 16, low_bits: int = 8,
+         last_high_ones: bool = False) -> np.ndarray:
+    """Keys whose bits above `low_bits` are constant over runs of `run`
+    consecutive indices (drawn once per run from stream 2); the low bits are
+    uniform (stream 1). With `last_high_ones` the last, possibly partial, run
+    has every high bit set."""
+    w = uniform(seed, n, key_bits, stream=1)
+    runs_n = -(-n // run) if n else 0
+    high = uniform(seed, runs_n, key_bits, stream=2)
+    if last_high_ones and runs_n:
+        high[-1] = np.iinfo(high.dtype).max
+    one = np.array(1, dtype=w.dtype)
+    low = (one << np.array(low_bits, dtype=w.dtype)) - one
+    return (np.repeat(high, run)[:n] & ~low) | (w & low)
+
+
 DISTRIBUTIONS = ("and1", "and2", "and3", "and4", "zipf", "presorted", "reverse", "distinct16")
 
 
