@@ -463,6 +463,45 @@ def per_kind_summary(per_kind, ow, lengths, limits, pair_bytes=8):
     return {"table": table, "dominant": (kind, avg_us, launches), "roofline": roof}
 
 
+def rts_baseline(ow, step, places, n, steps, stream, traced_configs, per_kind_times, onesweep_ms,
+                 d_kout, np):
+    """The reduce-then-scan baseline (Section 2: upsweep, tile scan and
+    downsweep per place, ~3pn memory operations against Onesweep's
+    ~(2p+1)n) timed on the same input, tile shape and buffers, right after
+    the Onesweep steps."""
+    import torch
+    k = max(3, min(steps, 10))
+    cfgs, holders = traced_configs(ow.ALGORITHM_REDUCE_THEN_SCAN, k + 1)
+    step(cfgs[0])  # warm-up
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for cfg in cfgs[1:]:
+        step(cfg)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / k
+    out = d_kout.cpu().numpy()
+    ok = bool(np.all(out[1:] >= out[:-1]))
+    if not ok:
+        log("[bench] ERROR: reduce-then-scan output is not sorted")
+        sys.exit(1)
+    per_kind = per_kind_times(holders[1:])
+    avg = {ow.KERNEL_NAMES[kind]: round(statistics.mean(ts) * 1e3, 2)
+           for kind, ts in sorted(per_kind.items())}
+    log(f"[bench] reduce-then-scan: {ms:.3f} ms per sort ({n / (ms * 1e-3) / 1e9:.2f} GKeys/s), "
+        f"Onesweep {onesweep_ms:.3f} ms; per-kernel avg us {avg}")
+    return {
+        "ms_per_step": round(ms, 4),
+        "value": round(n / (ms * 1e-3) / 1e9, 3),
+        "unit": "GKeys/s",
+        "steps": k,
+        "onesweep_speedup": round(ms / onesweep_ms, 3),
+        "memory_ops_ratio": round(3 * places / (2 * places + 1), 3),
+        "per_kernel_avg_us": avg,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -480,6 +519,11 @@ def main():
     ap.add_argument("--hist-blocks-per-cu", type=int, default=0)
     ap.add_argument("--rank", type=int, default=0, help="0 default, 1 ballot, 2 presence")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--algorithm", choices=("onesweep", "reduce-then-scan"), default="onesweep",
+                    help="algorithm of the timed sort (reduce-then-scan: the Section 2 "
+                         "baseline, for profiling it on its own)")
+    ap.add_argument("--no-rts-baseline", action="store_true",
+                    help="skip timing the reduce-then-scan baseline beside Onesweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run the library's plain copy kernel once on the input first "
                          "(known size: n keys read and written), for counter scaling")
@@ -517,28 +561,47 @@ def main():
     d_vout = torch.empty_like(d_vals) if has_vals else None
 
     places = key_bits // 8
-    launches_per_step = 3 + places + 1
     steps = args.steps
     stream = torch.cuda.current_stream()
+    algorithm = (ow.ALGORITHM_REDUCE_THEN_SCAN if args.algorithm == "reduce-then-scan"
+                 else ow.ALGORITHM_ONESWEEP)
 
-    # Per-launch HIP events on the stream the kernels run on.
-    traces, holders = [], []
-    for _ in range(steps):
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * launches_per_step)]
-        for e in evs:
-            e.record(stream)
-        arr = (ctypes.c_void_p * len(evs))(*[e.cuda_event for e in evs])
-        tr = ow.Trace()
-        tr.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
-        tr.capacity = launches_per_step
-        traces.append(tr)
-        holders.append((evs, arr))
+    def traced_configs(alg, count):
+        """`count` configs, each recording HIP events around every launch on
+        the stream the kernels run on."""
+        launches = 3 + places * (3 if alg == ow.ALGORITHM_REDUCE_THEN_SCAN else 1) + 1
+        cfgs, holders = [], []
+        for _ in range(count):
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * launches)]
+            for e in evs:
+                e.record(stream)
+            arr = (ctypes.c_void_p * len(evs))(*[e.cuda_event for e in evs])
+            tr = ow.Trace()
+            tr.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+            tr.capacity = launches
+            cfgs.append(ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu,
+                                       rank_algorithm=args.rank, algorithm=alg, trace=tr))
+            holders.append((tr, evs, arr))
+        return cfgs, holders
+
+    def per_kind_times(holders):
+        per_kind = {}
+        for tr, evs, _ in holders:
+            for i in range(tr.count):
+                per_kind.setdefault(tr.kinds[i], []).append(
+                    evs[2 * i].elapsed_time(evs[2 * i + 1]))
+        return per_kind
+
     cfg_plain = ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu,
-                               rank_algorithm=args.rank)
-    cfgs = [ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu,
-                           rank_algorithm=args.rank, trace=tr) for tr in traces]
-    temp = torch.empty(ow.sort_temp_bytes(n, key_bits, has_vals, config=cfg_plain),
-                       dtype=torch.uint8, device="cuda")
+                               rank_algorithm=args.rank, algorithm=algorithm)
+    cfgs, holders = traced_configs(algorithm, steps)
+    temp_bytes = ow.sort_temp_bytes(n, key_bits, has_vals, config=cfg_plain)
+    if not args.no_rts_baseline:
+        temp_bytes = max(temp_bytes, ow.sort_temp_bytes(
+            n, key_bits, has_vals, config=ow.make_config(
+                args.block, args.ipt, args.hist_blocks_per_cu, rank_algorithm=args.rank,
+                algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)))
+    temp = torch.empty(temp_bytes, dtype=torch.uint8, device="cuda")
 
     def step(cfg):
         if has_vals:
@@ -575,10 +638,7 @@ def main():
     log(f"[bench] {steps} steps in {ms_total:.3f} ms (wall {wall * 1e3:.1f} ms)")
 
     # Per-kernel durations from the traced events.
-    per_kind = {}
-    for tr, (evs, _) in zip(traces, holders):
-        for i in range(tr.count):
-            per_kind.setdefault(tr.kinds[i], []).append(evs[2 * i].elapsed_time(evs[2 * i + 1]))
+    per_kind = per_kind_times(holders)
     for kind, ts in sorted(per_kind.items()):
         log(f"[bench]   {ow.KERNEL_NAMES[kind]:9s} launches={len(ts):4d} "
             f"avg={statistics.mean(ts) * 1e3:9.2f} us  total/step={sum(ts) / steps * 1e3:9.2f} us")
@@ -592,11 +652,13 @@ def main():
 
     kb = key_bits // 8
     vb = 4 if has_vals else 0
-    bin_ts = per_kind.get(ow.KERNEL_BINNING, [])
+    scatter_kind = (ow.KERNEL_DOWNSWEEP if algorithm == ow.ALGORITHM_REDUCE_THEN_SCAN
+                    else ow.KERNEL_BINNING)
+    bin_ts = per_kind.get(scatter_kind, [])
     binning_avg_s = statistics.mean(bin_ts) * 1e-3 if bin_ts else float("nan")
     launch_bytes = n * 2 * (kb + vb)  # each binning pass reads and writes every element once
     achieved = launch_bytes / binning_avg_s / 1e9
-    traffic = read_traffic(launch_bytes)
+    traffic = read_traffic(launch_bytes) if algorithm == ow.ALGORITHM_ONESWEEP else None
     sort_bytes = n * kb + places * launch_bytes  # (2p+1)n element moves
     whole_gbs = sort_bytes / (ms_per_step * 1e-3) / 1e9
     log(f"[bench] whole sort: {whole_gbs:.1f} GB/s algorithmic = {whole_gbs / HBM_PEAK_GBS:.3f} "
@@ -627,12 +689,18 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "binning",
+            "kernel": ow.KERNEL_NAMES[scatter_kind],
             "algorithmic_bytes_per_launch": launch_bytes,
             "avg_launch_us": round(binning_avg_s * 1e6, 2),
         },
         "cpu_baseline": None,
     }
+    if algorithm != ow.ALGORITHM_ONESWEEP:
+        result["config"]["algorithm"] = "reduce-then-scan"
+    if not args.no_rts_baseline and algorithm == ow.ALGORITHM_ONESWEEP:
+        result["reduce_then_scan"] = rts_baseline(ow, step, places, n, steps, stream,
+                                                  traced_configs, per_kind_times, ms_per_step,
+                                                  d_kout, np)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(keys, vals)

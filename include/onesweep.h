@@ -67,8 +67,17 @@ typedef enum {
     ONESWEEP_KERNEL_BINNING = 3,   /* phase 3: one chained-scan binning pass */
     ONESWEEP_KERNEL_COPY = 4,      /* final copy when no pass (or an odd count) ran */
     ONESWEEP_KERNEL_CLASSIFY = 5,  /* segmented sort: offsets -> classes and tiles */
-    ONESWEEP_KERNEL_LDS_SORT = 6   /* segmented sort: whole segments sorted in LDS */
+    ONESWEEP_KERNEL_LDS_SORT = 6,  /* segmented sort: whole segments sorted in LDS */
+    ONESWEEP_KERNEL_UPSWEEP = 7,   /* reduce-then-scan: per-tile digit counts */
+    ONESWEEP_KERNEL_TILE_SCAN = 8, /* reduce-then-scan: prefix of counts over tiles */
+    ONESWEEP_KERNEL_DOWNSWEEP = 9  /* reduce-then-scan: rank and scatter one place */
 } onesweep_kernel_kind_t;
+
+/* Values of onesweep_config_t.algorithm. */
+typedef enum {
+    ONESWEEP_ALGORITHM_ONESWEEP = 0,        /* Section 3: chained-scan digit binning */
+    ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN = 1 /* Section 2 baseline: upsweep, scan, downsweep */
+} onesweep_algorithm_t;
 
 #define ONESWEEP_TRACE_MAX 64
 
@@ -112,6 +121,17 @@ typedef struct {
     int segment_streams;     /* segmented sort only: 0 = two streams when a batch has
                                 both LDS-sorted and tiled segments (see
                                 onesweep_sort_segments), 1 = the caller's stream only */
+    int algorithm;           /* onesweep_sort_keys/pairs only, onesweep_algorithm_t:
+                                0 = Onesweep; 1 = the reduce-then-scan baseline
+                                (Section 2, "Reduce-then-scan digit binning"): per
+                                digit place an upsweep that counts every tile's
+                                digits, a scan of those counts over tiles and a
+                                downsweep that ranks and scatters, ~3n memory
+                                operations per place instead of ~2n. Same output;
+                                built for the default tile shapes with ballot
+                                ranking (others: ONESWEEP_ERROR_UNSUPPORTED). The
+                                segmented sort and onesweep_binning_pass accept 0
+                                only (else ONESWEEP_ERROR_INVALID_VALUE). */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 

@@ -30,8 +30,9 @@ ERROR_HIP = 4
 ERROR_UNSUPPORTED = 5
 
 (KERNEL_RESET, KERNEL_HISTOGRAM, KERNEL_SCAN, KERNEL_BINNING, KERNEL_COPY, KERNEL_CLASSIFY,
- KERNEL_LDS_SORT) = range(7)
-KERNEL_NAMES = ("reset", "histogram", "scan", "binning", "copy", "classify", "lds_sort")
+ KERNEL_LDS_SORT, KERNEL_UPSWEEP, KERNEL_TILE_SCAN, KERNEL_DOWNSWEEP) = range(10)
+KERNEL_NAMES = ("reset", "histogram", "scan", "binning", "copy", "classify", "lds_sort",
+                "upsweep", "tile_scan", "downsweep")
 SEGMENT_CLASS_CAPACITY = (512, 2048, 8192)
 TRACE_MAX = 64
 RADIX_BITS = 8
@@ -47,7 +48,8 @@ class Config(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_int), ("block_threads", ctypes.c_int),
                 ("items_per_thread", ctypes.c_int), ("hist_blocks_per_cu", ctypes.c_int),
                 ("rank_algorithm", ctypes.c_int), ("segment_limits", ctypes.c_int * 3),
-                ("segment_streams", ctypes.c_int), ("trace", ctypes.POINTER(Trace))]
+                ("segment_streams", ctypes.c_int), ("algorithm", ctypes.c_int),
+                ("trace", ctypes.POINTER(Trace))]
 
 
 _vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
@@ -95,13 +97,15 @@ def _check(code: int):
 
 
 RANK_DEFAULT, RANK_BALLOT, RANK_PRESENCE, RANK_ATOMIC = 0, 1, 2, 3
+ALGORITHM_ONESWEEP, ALGORITHM_REDUCE_THEN_SCAN = 0, 1
 
 
 def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,
                 digit_bits: int = 0, rank_algorithm: int = 0, segment_limits=(0, 0, 0),
-                segment_streams: int = 0, trace: Trace | None = None) -> Config:
+                segment_streams: int = 0, algorithm: int = 0,
+                trace: Trace | None = None) -> Config:
     c = Config(digit_bits, block_threads, items_per_thread, hist_blocks_per_cu, rank_algorithm,
-               (ctypes.c_int * 3)(*segment_limits), segment_streams, None)
+               (ctypes.c_int * 3)(*segment_limits), segment_streams, algorithm, None)
     if trace is not None:
         c.trace = ctypes.pointer(trace)
     return c

@@ -69,13 +69,19 @@ onesweep_status_t device_cus(int *cus) {
 struct Resolved {
   BinningShape shape;
   int hist_blocks_per_cu;
+  int algorithm;  // onesweep_algorithm_t
   onesweep_trace_t *trace;
 };
 
+// Which entry point resolves: whole plain sorts offer both algorithms, the
+// segmented sort has its own binning shapes, the rest take Onesweep's.
+enum Caller { kCallSort, kCallSegments, kCallOther };
+
 onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const onesweep_config_t *cfg,
-                          Resolved *r, bool segmented = false) {
+                          Resolved *r, Caller caller = kCallOther) {
   r->shape = binning_default_shape(key_bits, has_values, n);
   r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
+  r->algorithm = ONESWEEP_ALGORITHM_ONESWEEP;
   r->trace = nullptr;
   if (cfg != nullptr) {
     if (cfg->digit_bits != 0 && cfg->digit_bits != kRadixBits)
@@ -90,16 +96,27 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
       return fail(ONESWEEP_ERROR_INVALID_VALUE, "rank_algorithm %d not in [0, 3]",
                   cfg->rank_algorithm);
     if (cfg->rank_algorithm != 0) r->shape.rank = cfg->rank_algorithm - 1;
+    if (cfg->algorithm != ONESWEEP_ALGORITHM_ONESWEEP &&
+        cfg->algorithm != ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "algorithm %d not 0 or 1", cfg->algorithm);
+    if (cfg->algorithm != ONESWEEP_ALGORITHM_ONESWEEP && caller != kCallSort)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE,
+                  "algorithm %d: reduce-then-scan is offered by whole plain sorts only",
+                  cfg->algorithm);
+    r->algorithm = cfg->algorithm;
     r->trace = cfg->trace;
     if (r->trace && (r->trace->capacity < 0 || r->trace->capacity > ONESWEEP_TRACE_MAX ||
                      (r->trace->capacity > 0 && r->trace->events == nullptr)))
       return fail(ONESWEEP_ERROR_INVALID_VALUE, "trace capacity/events invalid");
   }
-  if (!binning_shape_supported(r->shape, segmented))
+  const bool rts = r->algorithm == ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN;
+  const int mode = caller == kCallSegments ? kBinSegmented : (rts ? kBinDownsweep : kBinChained);
+  if (!binning_shape_supported(r->shape, mode) ||
+      (rts && !upsweep_shape_supported(key_bits, r->shape.block, r->shape.ipt)))
     return fail(ONESWEEP_ERROR_UNSUPPORTED,
                 "%sbinning shape (key_bits=%d, values=%d, block=%d, items=%d, rank=%d) not built",
-                segmented ? "segmented " : "", key_bits, (int)has_values, r->shape.block,
-                r->shape.ipt, r->shape.rank + 1);
+                mode == kBinSegmented ? "segmented " : (rts ? "reduce-then-scan " : ""),
+                key_bits, (int)has_values, r->shape.block, r->shape.ipt, r->shape.rank + 1);
   return ONESWEEP_SUCCESS;
 }
 
@@ -112,7 +129,11 @@ struct SortLayout {
   size_t status_words_per_place;
 };
 
-SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size_t tile) {
+// Reduce-then-scan keeps one count table of the same size as a place's
+// status words, reused by every place and not cleared (the upsweep writes
+// every entry).
+SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size_t tile,
+                       bool rts = false) {
   SortLayout L{};
   L.tiles = static_cast<uint32_t>((n + tile - 1) / tile);
   L.status_words_per_place = static_cast<size_t>(L.tiles) * kRadix;
@@ -122,8 +143,13 @@ SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size
   L.counters = off;
   off += kAlign;
   L.status = off;
-  off += align_up(sizeof(uint32_t) * L.status_words_per_place * places);
-  L.zero_end = off;
+  if (rts) {
+    L.zero_end = off;
+    off += align_up(sizeof(uint32_t) * L.status_words_per_place * (places > 0 ? 1 : 0));
+  } else {
+    off += align_up(sizeof(uint32_t) * L.status_words_per_place * places);
+    L.zero_end = off;
+  }
   L.offsets = off;
   off += align_up(sizeof(uint32_t) * kMaxPlaces * kRadix);
   L.plan = off;
@@ -192,10 +218,11 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
   onesweep_status_t st = check_common(temp_bytes, n, key_bits, begin_bit, end_bit);
   if (st) return st;
   Resolved rc;
-  if ((st = resolve(key_bits, has_values, n, cfg, &rc))) return st;
+  if ((st = resolve(key_bits, has_values, n, cfg, &rc, kCallSort))) return st;
   const int places = num_places(begin_bit, end_bit);
   const size_t tile = binning_tile_items(rc.shape);
-  const SortLayout L = sort_layout(n, key_bits, has_values, places, tile);
+  const bool rts = rc.algorithm == ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN;
+  const SortLayout L = sort_layout(n, key_bits, has_values, places, tile, rts);
   if (d_temp == nullptr) {
     *temp_bytes = L.total;
     return ONESWEEP_SUCCESS;
@@ -277,34 +304,65 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
   for (int j = 0; j < places; ++j) {
     const int lo = begin_bit + j * kRadixBits;
     const int width = (lo + kRadixBits <= end_bit) ? kRadixBits : end_bit - lo;
+    // Onesweep: place j's own status words; reduce-then-scan: the shared
+    // count table, filled by the upsweep and scanned before the downsweep.
+    uint32_t *table = rts ? status : status + j * L.status_words_per_place;
+    const int mode = rts ? kBinDownsweep : kBinChained;
+    const int kind = rts ? ONESWEEP_KERNEL_DOWNSWEEP : ONESWEEP_KERNEL_BINNING;
     if (key_bits == 32) {
+      if (rts) {
+        UpsweepArgs<uint32_t> u{};
+        for (int b = 0; b < 3; ++b) u.keys[b] = static_cast<uint32_t *>(ca.keys[b]);
+        u.plan = plan;
+        u.counts = table;
+        u.n = static_cast<uint32_t>(n);
+        u.place = j;
+        u.shift = lo;
+        u.width = width;
+        ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_UPSWEEP, "upsweep",
+                        launch_upsweep(32, rc.shape.block, rc.shape.ipt, &u, L.tiles, stream));
+        ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_TILE_SCAN, "tile scan",
+                        launch_tile_scan(table, L.tiles, plan, j, stream));
+      }
       BinningArgs<uint32_t> a{};
       for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<uint32_t *>(ca.keys[b]);
       for (int b = 0; b < 3; ++b) a.vals[b] = ca.vals[b];
       a.bin_offsets = offsets + j * kRadix;
-      a.status = status + j * L.status_words_per_place;
+      a.status = table;
       a.tile_counter = counters + j;
       a.plan = plan;
       a.n = static_cast<uint32_t>(n);
       a.place = j;
       a.shift = lo;
       a.width = width;
-      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                      launch_binning(rc.shape, false, &a, L.tiles, stream));
+      ONESWEEP_LAUNCH(tr, kind, "binning", launch_binning(rc.shape, mode, &a, L.tiles, stream));
     } else {
+      if (rts) {
+        UpsweepArgs<uint64_t> u{};
+        for (int b = 0; b < 3; ++b) u.keys[b] = static_cast<uint64_t *>(ca.keys[b]);
+        u.plan = plan;
+        u.counts = table;
+        u.n = static_cast<uint32_t>(n);
+        u.place = j;
+        u.shift = lo;
+        u.width = width;
+        ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_UPSWEEP, "upsweep",
+                        launch_upsweep(64, rc.shape.block, rc.shape.ipt, &u, L.tiles, stream));
+        ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_TILE_SCAN, "tile scan",
+                        launch_tile_scan(table, L.tiles, plan, j, stream));
+      }
       BinningArgs<uint64_t> a{};
       for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<uint64_t *>(ca.keys[b]);
       for (int b = 0; b < 3; ++b) a.vals[b] = ca.vals[b];
       a.bin_offsets = offsets + j * kRadix;
-      a.status = status + j * L.status_words_per_place;
+      a.status = table;
       a.tile_counter = counters + j;
       a.plan = plan;
       a.n = static_cast<uint32_t>(n);
       a.place = j;
       a.shift = lo;
       a.width = width;
-      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                      launch_binning(rc.shape, false, &a, L.tiles, stream));
+      ONESWEEP_LAUNCH(tr, kind, "binning", launch_binning(rc.shape, mode, &a, L.tiles, stream));
     }
   }
   ca.plan = plan;
@@ -454,7 +512,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   if (num_segments == 0 && n != 0)
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "%zu keys but no segment", n);
   Resolved rc;
-  if ((st = resolve(key_bits, has_values, n, cfg, &rc, true))) return st;
+  if ((st = resolve(key_bits, has_values, n, cfg, &rc, kCallSegments))) return st;
   uint32_t limit[kSegClasses];
   if ((st = segment_limits(cfg, limit))) return st;
   const int places = num_places(begin_bit, end_bit);
@@ -656,7 +714,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
       a.shift = lo;
       a.width = width;
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "segment binning",
-                      launch_binning(rc.shape, true, &a, L.max_tiles, stream));
+                      launch_binning(rc.shape, kBinSegmented, &a, L.max_tiles, stream));
     } else {
       BinningArgs<uint64_t> a{};
       a.keys[kBufIn] = static_cast<uint64_t *>(kbuf[from]);
@@ -671,7 +729,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
       a.shift = lo;
       a.width = width;
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "segment binning",
-                      launch_binning(rc.shape, true, &a, L.max_tiles, stream));
+                      launch_binning(rc.shape, kBinSegmented, &a, L.max_tiles, stream));
     }
   }
   if (buffer_after(places) != kBufOut) {
@@ -818,7 +876,7 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.shift = shift;
     a.width = width;
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                    launch_binning(rc.shape, false, &a, tiles, s));
+                    launch_binning(rc.shape, kBinChained, &a, tiles, s));
   } else {
     BinningArgs<uint64_t> a{};
     a.keys[kBufIn] = static_cast<uint64_t *>(const_cast<void *>(d_src_keys));
@@ -834,7 +892,7 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.shift = shift;
     a.width = width;
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "binning",
-                    launch_binning(rc.shape, false, &a, tiles, s));
+                    launch_binning(rc.shape, kBinChained, &a, tiles, s));
   }
   return ONESWEEP_SUCCESS;
 }
@@ -955,7 +1013,7 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
 size_t onesweep_tile_items(int key_bits, int has_values, size_t n, const onesweep_config_t *cfg) {
   if (key_bits != 32 && key_bits != 64) return 0;
   Resolved rc;
-  if (resolve(key_bits, has_values != 0, n, cfg, &rc) != ONESWEEP_SUCCESS) return 0;
+  if (resolve(key_bits, has_values != 0, n, cfg, &rc, kCallSort) != ONESWEEP_SUCCESS) return 0;
   return binning_tile_items(rc.shape);
 }
 

@@ -69,12 +69,17 @@ constexpr int binning_waves_per_eu() {
              : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
 }
 
-// kSeg: the tiles belong to the large segments of a segmented sort (each
-// segment its own chained scan and bin offsets); otherwise to one sequence.
-template <typename K, bool kVals, int kBlock, int kIpt, int kRank, bool kSeg>
+// kMode: kBinChained, one sequence with a chained scan over its tiles;
+// kBinSegmented, the tiles of the large segments of a segmented sort (each
+// segment its own chained scan and bin offsets); kBinDownsweep, the scatter
+// step of reduce-then-scan: every tile's exclusive prefix per digit is read
+// from a table that the upsweep and tile-scan kernels filled beforehand.
+template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(binning_waves_per_eu<K, kIpt>())))
     binning_kernel(BinningArgs<K> a) {
+  constexpr bool kSeg = kMode == kBinSegmented;
+  constexpr bool kRts = kMode == kBinDownsweep;
   constexpr int kWaves = kBlock / kWave;
   constexpr int kTile = kBlock * kIpt;
   constexpr int kWaveItems = kWave * kIpt;
@@ -96,8 +101,8 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int kEntryWords = kRank == kRankPresence ? 4 : 1;
   // One-digit tiles skip the LDS regrouping and write keys and values from
   // registers. Built for 32-bit pairs only, where it is measured faster;
-  // keys-only tiles gain nothing from it (the pass waits on the look-back,
-  // not on LDS), and 64-bit pairs would spill holding their keys across the
+  // keys-only tiles gain nothing from it (the pass waits on memory, not on
+  // LDS), and 64-bit pairs would spill holding their keys across the
   // look-back.
   constexpr bool kShortCircuit = sizeof(K) == 4 && kVals;
   constexpr size_t kKeyBytes = sizeof(K) * kTile;
@@ -133,7 +138,8 @@ __global__ void __launch_bounds__(kBlock)
       z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   if (tid == 0) {
-    s_tile = atomicAdd(a.tile_counter, 1u);
+    // reduce-then-scan tiles depend on no other tile: the block index serves
+    s_tile = kRts ? blockIdx.x : atomicAdd(a.tile_counter, 1u);
     s_uniform = 0u;
   }
   __syncthreads();
@@ -265,8 +271,9 @@ __global__ void __launch_bounds__(kBlock)
       s_uniform = 1u + static_cast<uint32_t>(tid);
     // 4a. Publish this tile's count (a first tile's count is already its
     // prefix).
-    store_status(&a.status[static_cast<size_t>(tile) * kRadix + tid],
-                 (first ? kFlagG : kFlagL) | published);
+    if constexpr (!kRts)
+      store_status(&a.status[static_cast<size_t>(tile) * kRadix + tid],
+                   (first ? kFlagG : kFlagL) | published);
     uint32_t incl = total;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -313,7 +320,11 @@ __global__ void __launch_bounds__(kBlock)
   if (tid < kRadix) {
     const uint32_t bin_start = bin_base + bin_offsets[tid];
     uint32_t exclusive = 0u;
-    if (!first) {
+    if constexpr (kRts) {
+      // digit-major table of exclusive prefixes over tiles
+      const uint32_t tiles = (n + static_cast<uint32_t>(kTile) - 1u) / static_cast<uint32_t>(kTile);
+      exclusive = a.status[static_cast<size_t>(tid) * tiles + tile];
+    } else if (!first) {
       int pred = static_cast<int>(tile) - 1;
       while (true) {
         uint32_t s[kLookback];
@@ -482,14 +493,32 @@ __global__ void __launch_bounds__(kBlock)
   X(uint64_t, true, 512, 8, 0)             \
   X(uint64_t, true, 1024, 8, 0)
 
+// Shapes built for the reduce-then-scan baseline (ballot ranking): the
+// default shapes of every key width and value presence.
+#define ONESWEEP_DOWNSWEEP_SHAPES(X) \
+  X(uint32_t, false, 256, 8, 0)      \
+  X(uint32_t, true, 256, 8, 0)       \
+  X(uint32_t, false, 512, 16, 0)     \
+  X(uint32_t, true, 512, 16, 0)      \
+  X(uint32_t, false, 1024, 8, 0)     \
+  X(uint32_t, true, 1024, 8, 0)      \
+  X(uint64_t, false, 256, 8, 0)      \
+  X(uint64_t, true, 256, 8, 0)       \
+  X(uint64_t, false, 512, 8, 0)      \
+  X(uint64_t, true, 512, 8, 0)       \
+  X(uint64_t, false, 1024, 8, 0)     \
+  X(uint64_t, true, 1024, 8, 0)
+
 #define ONESWEEP_SHAPE_IS(K, V, B, I, R) \
   (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I && s.rank == R)
 
-bool binning_shape_supported(const BinningShape &s, bool segmented) {
+bool binning_shape_supported(const BinningShape &s, int mode) {
 #define ONESWEEP_MATCH(K, V, B, I, R) \
   if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) return true;
-  if (segmented) {
+  if (mode == kBinSegmented) {
     ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_MATCH)
+  } else if (mode == kBinDownsweep) {
+    ONESWEEP_DOWNSWEEP_SHAPES(ONESWEEP_MATCH)
   } else {
     ONESWEEP_BINNING_SHAPES(ONESWEEP_MATCH)
   }
@@ -518,21 +547,25 @@ BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
   return BinningShape{32, has_values, 1024, 8, kRankBallot};
 }
 
-hipError_t launch_binning(const BinningShape &s, bool segmented, const void *args,
-                          uint32_t grid, hipStream_t stream) {
-#define ONESWEEP_LAUNCH(K, V, B, I, R, SEG)                                             \
-  if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) {                                                \
-    hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, SEG>), dim3(grid), dim3(B), 0, stream, \
-                       *static_cast<const BinningArgs<K> *>(args));                      \
-    return hipGetLastError();                                                            \
+hipError_t launch_binning(const BinningShape &s, int mode, const void *args, uint32_t grid,
+                          hipStream_t stream) {
+#define ONESWEEP_LAUNCH(K, V, B, I, R, MODE)                                             \
+  if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) {                                                 \
+    hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, MODE>), dim3(grid), dim3(B), 0, stream, \
+                       *static_cast<const BinningArgs<K> *>(args));                       \
+    return hipGetLastError();                                                             \
   }
-#define ONESWEEP_LAUNCH_FLAT(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, false)
-#define ONESWEEP_LAUNCH_SEG(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, true)
-  if (segmented) {
+#define ONESWEEP_LAUNCH_FLAT(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinChained)
+#define ONESWEEP_LAUNCH_SEG(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinSegmented)
+#define ONESWEEP_LAUNCH_DOWN(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinDownsweep)
+  if (mode == kBinSegmented) {
     ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_LAUNCH_SEG)
+  } else if (mode == kBinDownsweep) {
+    ONESWEEP_DOWNSWEEP_SHAPES(ONESWEEP_LAUNCH_DOWN)
   } else {
     ONESWEEP_BINNING_SHAPES(ONESWEEP_LAUNCH_FLAT)
   }
+#undef ONESWEEP_LAUNCH_DOWN
 #undef ONESWEEP_LAUNCH_SEG
 #undef ONESWEEP_LAUNCH_FLAT
 #undef ONESWEEP_LAUNCH

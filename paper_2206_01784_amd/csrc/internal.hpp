@@ -28,16 +28,41 @@ struct BinningShape {
   int rank;
 };
 
-// `segmented`: the variant whose tiles are those of a segmented sort's large
-// segments (BinningArgs::seg); fewer shapes are built for it.
-bool binning_shape_supported(const BinningShape &s, bool segmented);
+// Binning kernel modes: Onesweep's chained scan over the tiles of one
+// sequence; the same per large segment of a segmented sort
+// (BinningArgs::seg); or the scatter (downsweep) step of the reduce-then-scan
+// baseline. Fewer shapes are built for the last two.
+enum BinningMode : int { kBinChained = 0, kBinSegmented = 1, kBinDownsweep = 2 };
+
+bool binning_shape_supported(const BinningShape &s, int mode);
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n);
 // Keys per binning tile of a shape.
 size_t binning_tile_items(const BinningShape &s);
 
 // `args` points to BinningArgs<uint32_t> or BinningArgs<uint64_t>.
-hipError_t launch_binning(const BinningShape &s, bool segmented, const void *args,
+hipError_t launch_binning(const BinningShape &s, int mode, const void *args,
                           uint32_t grid, hipStream_t stream);
+
+// Reduce-then-scan baseline, per place: the upsweep counts every tile's
+// digits into a digit-major table [256][tiles]; the tile scan turns each
+// digit's row into exclusive prefixes over tiles in place. Both follow the
+// pass plan (a skipped place does nothing). The tile shape is the
+// downsweep's.
+template <typename K>
+struct UpsweepArgs {
+  K *keys[3];
+  const PassPlan *plan;
+  uint32_t *counts;  // [256][tiles]
+  uint32_t n;
+  int place;
+  int shift;
+  int width;
+};
+bool upsweep_shape_supported(int key_bits, int block, int ipt);
+hipError_t launch_upsweep(int key_bits, int block, int ipt, const void *args, uint32_t tiles,
+                          hipStream_t stream);
+hipError_t launch_tile_scan(uint32_t *counts, uint32_t tiles, const PassPlan *plan, int place,
+                            hipStream_t stream);
 
 // Histogram of all places (phase 1), persistent tile-cyclic grid.
 constexpr int kHistBlock = 256;

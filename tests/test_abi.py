@@ -82,6 +82,49 @@ def test_unsupported_config_is_rejected():
     assert rc == ow.ERROR_UNSUPPORTED
 
 
+def test_reduce_then_scan_config_validation_needs_no_gpu():
+    """The baseline algorithm: accepted by whole plain sorts for the shapes
+    built for it; rejected elsewhere and for unknown values; its temporary
+    storage holds one count table instead of one status table per place."""
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    rts = ow.make_config(algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)
+    n = 1 << 28
+    t = ow.tile_items(32, False, rts, n)
+    assert t == ow.tile_items(32, False, None, n)
+    tiles = -(-n // t)
+    one = ow.sort_temp_bytes(n, 32, config=rts)
+    assert one >= 4 * n + tiles * 256 * 4
+    assert ow.sort_temp_bytes(n, 32) - one >= 3 * tiles * 256 * 4
+    for kb in (32, 64):
+        for vals in (False, True):
+            for log2n in (12, 20, 28):
+                assert ow.sort_temp_bytes(1 << log2n, kb, vals, config=rts) > 0
+    size = ctypes.c_size_t(0)
+    for alg in (-1, 2):
+        cfg = ow.make_config(algorithm=alg)
+        rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
+                                    ctypes.byref(cfg), None)
+        assert rc == ow.ERROR_INVALID_VALUE, alg
+    # shapes not built for the baseline
+    for shape in ((512, 12), (256, 16)):
+        cfg = ow.make_config(*shape, algorithm=1)
+        rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
+                                    ctypes.byref(cfg), None)
+        assert rc == ow.ERROR_UNSUPPORTED, shape
+    cfg = ow.make_config(rank_algorithm=ow.RANK_PRESENCE, algorithm=1)
+    rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
+                                ctypes.byref(cfg), None)
+    assert rc == ow.ERROR_UNSUPPORTED
+    # the segmented sort and the single-pass entry point take Onesweep only
+    rc = lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, None, None, 10, None, 1,
+                                    32, 0, 32, 1, ctypes.byref(rts), None)
+    assert rc == ow.ERROR_INVALID_VALUE
+    rc = lib.onesweep_binning_pass(None, ctypes.byref(size), None, None, None, None, 10, 32, 0, 8,
+                                   None, ctypes.byref(rts), None)
+    assert rc == ow.ERROR_INVALID_VALUE
+
+
 def test_insufficient_temp_and_null_pointers():
     import paper_2206_01784_amd as ow
     lib = ow.library()

@@ -149,9 +149,10 @@ def test_sort_distributions(ow, kb, dist):
 @pytest.mark.parametrize("rank", RANKS)
 def test_one_digit_tiles(ow, kb, vals, rank):
     """Tiles whose keys share the place's digit take the short-circuit write
-    (Section 3.3): runs of a tile's length and of other lengths, so tiles are
-    one-digit, mixed, or straddle two runs; the ragged last tile's real keys
-    all carry the padding digit (it must not short-circuit)."""
+    (Section 3, chained-scan digit-binning kernel): runs of a tile's length
+    and of other lengths, so tiles are one-digit, mixed, or straddle two
+    runs; the ragged last tile's real keys all carry the padding digit (it
+    must not short-circuit)."""
     for block, ipt in SHAPES[(kb, vals)]:
         cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=rank)
         T = ow.tile_items(kb, vals, cfg)
@@ -264,3 +265,112 @@ def test_graph_capture_replays(ow):
         eager = ow.sort_keys(dev(keys[: n // 2]))
         torch.cuda.synchronize()
         assert np.array_equal(host(eager), oracle.sort(keys[: n // 2])[0])
+
+
+# ------------------------------------------------------------------ reduce-then-scan baseline
+
+RTS_SHAPES = {
+    32: [(256, 8), (512, 16), (1024, 8)],
+    64: [(256, 8), (512, 8), (1024, 8)],
+}
+
+
+@pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
+def test_reduce_then_scan_sorts(ow, kb, vals):
+    """The Section 2 baseline gives the same unique stable result: every shape
+    built for it, ragged sizes, skewed and one-digit-place inputs (skipped
+    places, odd pass counts), partial bit ranges and in-place sorts."""
+    for block, ipt in RTS_SHAPES[kb]:
+        cfg = ow.make_config(block, ipt, algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)
+        T = ow.tile_items(kb, vals, cfg)
+        assert T == block * ipt
+        for n in (1, T - 1, T + 1, 7 * T + 333):
+            keys = W.uniform(41 + n % 11, n, kb)
+            v = np.arange(n, dtype=np.uint32) if vals else None
+            check_sort(ow, keys, v, 0, kb, cfg)
+        n = 3 * T + 5
+        v = np.arange(n, dtype=np.uint32) if vals else None
+        for dist in ("and4", "equal", "distinct16", "presorted"):
+            check_sort(ow, keys_of(dist, 43, n, kb), v, 0, kb, cfg)
+        check_sort(ow, W.runs(44, n, kb, run=T), v, 0, kb, cfg)
+        keys = W.uniform(45, n, kb)
+        for begin, end in ((0, 1), (3, 11), (8, 16), (kb - 13, kb), (7, 7)):
+            check_sort(ow, keys, v, begin, end, cfg)
+        check_sort(ow, keys, v, 0, kb, cfg, inplace=True)
+
+
+def test_reduce_then_scan_count_table(ow):
+    """After the sort, the shared count table holds the last place's tile scan:
+    row v, column t is the number of keys with digit v in tiles before t of
+    that pass's input, i.e. the oracle's chained-scan inclusive prefix of tile
+    t - 1 (Figure 4's prefix order within one digit)."""
+    cfg = ow.make_config(1024, 8, algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)
+    T = ow.tile_items(32, False, cfg)
+    n = 5 * T + 77
+    keys = W.uniform(47, n)
+    temp = torch.empty(ow.sort_temp_bytes(n, config=cfg), dtype=torch.uint8, device="cuda")
+    out = ow.sort_keys(dev(keys), temp=temp, config=cfg)
+    assert np.array_equal(host(out), oracle.sort(keys)[0])
+    pass_in = oracle.sort(keys, None, 0, 24, 8)[0]
+    incl = (oracle.pass_status(pass_in, 24, 8, T) & np.uint32(0x3FFFFFFF)).astype(np.uint32)
+    g = incl.shape[0]
+    excl = np.vstack([np.zeros((1, 256), dtype=np.uint32), incl[:-1]])
+    # temp layout: 8 x 256 histogram words, one 256-byte counter slot, then the table
+    table = host(temp[8448:8448 + 256 * g * 4].view(torch.uint32)).reshape(256, g)
+    assert np.array_equal(table, excl.T)
+
+
+def test_reduce_then_scan_trace_and_graph_replay(ow):
+    """Launch sequence per place: upsweep, tile scan, downsweep; a captured
+    graph replays exactly with new keys."""
+    import ctypes
+    n = (1 << 18) + 7
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * 32)]
+    for e in events:
+        e.record()
+    torch.cuda.synchronize()
+    arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+    tr = ow.Trace()
+    tr.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    tr.capacity = 32
+    cfg = ow.make_config(algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN, trace=tr)
+    keys = W.uniform(49, n)
+    out = ow.sort_keys(dev(keys), config=cfg)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(out), oracle.sort(keys)[0])
+    kinds = [tr.kinds[i] for i in range(tr.count)]
+    assert kinds == [ow.KERNEL_RESET, ow.KERNEL_HISTOGRAM, ow.KERNEL_SCAN] + \
+        [ow.KERNEL_UPSWEEP, ow.KERNEL_TILE_SCAN, ow.KERNEL_DOWNSWEEP] * 4 + [ow.KERNEL_COPY]
+
+    cfg = ow.make_config(algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)
+    static_in = torch.empty(n, dtype=torch.uint32, device="cuda")
+    static_vals = torch.empty(n, dtype=torch.uint32, device="cuda")
+    static_out = torch.empty_like(static_in)
+    static_vout = torch.empty_like(static_in)
+    temp = torch.empty(ow.sort_temp_bytes(n, 32, True, config=cfg), dtype=torch.uint8,
+                       device="cuda")
+    static_in.copy_(dev(keys))
+    static_vals.copy_(dev(np.arange(n, dtype=np.uint32)))
+    ow.sort_pairs(static_in, static_vals, keys_out=static_out, values_out=static_vout, temp=temp,
+                  config=cfg)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            ow.sort_pairs(static_in, static_vals, keys_out=static_out, values_out=static_vout,
+                          temp=temp, config=cfg, stream=s)
+    torch.cuda.synchronize()
+    vals = np.arange(n, dtype=np.uint32)
+    for seed in (51, 52, 53):
+        k = W.and_of_q(seed, 1 + seed % 3, n)
+        static_in.copy_(dev(k))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        wk, wv = oracle.sort(k, vals)
+        assert np.array_equal(host(static_out), wk), seed
+        assert np.array_equal(host(static_vout), wv), seed
+        eager = ow.sort_keys(dev(k[: n // 3]), config=cfg)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(eager), oracle.sort(k[: n // 3])[0])
