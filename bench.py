@@ -35,6 +35,9 @@ WORKLOADS = {
     "u32_keys_and3": (32, False, "and3", 28),
     "u32_keys_and4": (32, False, "and4", 28),
     "u32_keys_equal": (32, False, "equal", 28),
+    "u32_keys_and8": (32, False, "and8", 28),
+    "u32_keys_and16": (32, False, "and16", 28),
+    "u64_keys_uniform": (64, False, "uniform", 27),
     "u32_pairs_uniform": (32, True, "uniform", 28),
     "u64_pairs_uniform": (64, True, "uniform", 27),
     "u32_keys_uniform_2p20": (32, False, "uniform", 20),

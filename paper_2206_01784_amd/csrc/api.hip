@@ -131,7 +131,7 @@ struct SortLayout {
 
 // Reduce-then-scan keeps one count table of the same size as a place's
 // status words, reused by every place and not cleared (the upsweep writes
-// every entry).
+// every entry); only the histograms and tile counters are cleared.
 SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size_t tile,
                        bool rts = false) {
   SortLayout L{};

@@ -138,8 +138,11 @@ __global__ void __launch_bounds__(kBlock)
       z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   if (tid == 0) {
-    // reduce-then-scan tiles depend on no other tile: the block index serves
-    s_tile = kRts ? blockIdx.x : atomicAdd(a.tile_counter, 1u);
+    // Tiles in the order workgroups start, in every mode: workgroups are
+    // spread over the XCDs out of block-index order, and a downsweep that
+    // used block indices (it needs no ordering) scatters 15-50% slower, its
+    // concurrent tiles writing far-apart parts of each bin.
+    s_tile = atomicAdd(a.tile_counter, 1u);
     s_uniform = 0u;
   }
   __syncthreads();

@@ -19,22 +19,25 @@
 
 namespace onesweep {
 
-// One workgroup per tile (the downsweep's tile shape and order): per-wave LDS
-// counters, one LDS atomic per key, then each digit's total over the waves is
-// written to row `digit` of the digit-major count table.
+// One workgroup per tile (the downsweep's tile shape and order): LDS
+// counters, one LDS atomic per key, then each digit's total is written to row
+// `digit` of the digit-major count table. kCopies interleaved copies of each
+// counter (copy = lane % kCopies, copy index fastest) keep lanes that share a
+// digit on different banks, bounding same-address serialisation of skewed
+// inputs to 64 / kCopies-way within one atomic instruction.
 template <typename K, int kBlock, int kIpt>
 __global__ void __launch_bounds__(kBlock) upsweep_kernel(UpsweepArgs<K> a) {
-  constexpr int kWaves = kBlock / kWave;
+  constexpr int kCopies = 8;
   constexpr int kTile = kBlock * kIpt;
   constexpr int kWaveItems = kWave * kIpt;
-  __shared__ uint32_t s_count[kWaves * kRadix];
+  __shared__ uint32_t s_count[kRadix * kCopies];
   if (a.plan->run[a.place] == 0u) return;  // skipped place: no table is read
   const K *__restrict__ src = a.keys[a.plan->src[a.place]];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  for (int i = tid; i < kWaves * kRadix; i += kBlock) s_count[i] = 0u;
+  for (int i = tid; i < kRadix * kCopies; i += kBlock) s_count[i] = 0u;
   __syncthreads();
 
   const uint32_t tile = blockIdx.x;
@@ -45,30 +48,30 @@ __global__ void __launch_bounds__(kBlock) upsweep_kernel(UpsweepArgs<K> a) {
   const uint32_t wb = base + static_cast<uint32_t>(wave * kWaveItems + lane);
   const int shift = a.shift;
   const uint32_t mask = (1u << a.width) - 1u;
-  uint32_t *table = s_count + wave * kRadix;
+  uint32_t *mine = s_count + (lane & (kCopies - 1));
   K key[kIpt];
   if (count == static_cast<uint32_t>(kTile)) {
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) key[i] = src[wb + i * kWave];
 #pragma unroll
     for (int i = 0; i < kIpt; ++i)
-      __hip_atomic_fetch_add(&table[digit_of(key[i], shift, mask)], 1u, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(&mine[digit_of(key[i], shift, mask) * kCopies], 1u,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   } else {
     const uint32_t end = base + count;
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t idx = wb + i * kWave;
       if (idx < end)
-        __hip_atomic_fetch_add(&table[digit_of(src[idx], shift, mask)], 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&mine[digit_of(src[idx], shift, mask) * kCopies], 1u,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
   __syncthreads();
   if (tid < kRadix) {
     uint32_t total = 0u;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) total += s_count[w * kRadix + tid];
+    for (int c = 0; c < kCopies; ++c) total += s_count[tid * kCopies + c];
     a.counts[static_cast<size_t>(tid) * tiles + tile] = total;
   }
 }
