@@ -73,6 +73,15 @@ typedef enum {
     ONESWEEP_KERNEL_DOWNSWEEP = 9  /* reduce-then-scan: rank and scatter one place */
 } onesweep_kernel_kind_t;
 
+/* Values of onesweep_config_t.key_type: how the key bits are ordered. */
+typedef enum {
+    ONESWEEP_KEY_UNSIGNED = 0, /* unsigned integers */
+    ONESWEEP_KEY_SIGNED = 1,   /* two's-complement integers */
+    ONESWEEP_KEY_FLOAT = 2     /* IEEE 754 binary32 (32-bit keys) or binary64 (64-bit):
+                                  -NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN, NaNs
+                                  by payload bits */
+} onesweep_key_type_t;
+
 /* Values of onesweep_config_t.algorithm. */
 typedef enum {
     ONESWEEP_ALGORITHM_ONESWEEP = 0,        /* Section 3: chained-scan digit binning */
@@ -132,6 +141,18 @@ typedef struct {
                                 ranking (others: ONESWEEP_ERROR_UNSUPPORTED). The
                                 segmented sort and onesweep_binning_pass accept 0
                                 only (else ONESWEEP_ERROR_INVALID_VALUE). */
+    int key_type;            /* onesweep_key_type_t. Signed and floating-point keys
+                                are ordered through a bit transform that maps their
+                                order onto unsigned order (Section 3 names such
+                                transforms for signed and floating-point keys): the
+                                sign bit is flipped, and negative floating-point keys
+                                have every bit flipped. Keys are stored unchanged;
+                                the transform only decides digits, so begin_bit and
+                                end_bit select bits of the transformed key. Applies to
+                                every entry point that takes a config. */
+    int descending;          /* 1: descending order (digits of the complemented
+                                transformed key), still stable: equal keys keep their
+                                input order. 0: ascending. */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 
@@ -158,7 +179,8 @@ onesweep_status_t onesweep_sort_pairs(void *d_temp, size_t *temp_bytes, const vo
 
 /*
  * Phase 1 alone (Section 3, upfront histogram kernel): d_hist[j * 256 + v]
- * receives the number of keys whose digit at place j is v, for all
+ * receives the number of keys whose digit at place j is v (digits of the
+ * key bits as cfg's key_type and descending order them), for all
  * p = ceil((end_bit - begin_bit) / 8) places. d_hist must hold p * 256
  * uint32 words; it is cleared first. n < 2^30.
  */
@@ -169,7 +191,8 @@ onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits,
 /*
  * Phase 3, one binning iteration (Section 3, chained scan digit-binning
  * kernel): stably scatter the n keys (and values, when d_src_vals is not
- * NULL) of src into dst by the digit (key >> shift) & (2^width - 1), with
+ * NULL) of src into dst by the digit (k >> shift) & (2^width - 1), where k
+ * is the key's bits as cfg's key_type and descending order them, with
  * d_bin_offsets[v] (256 uint32, device) the global start of bin v, which is
  * the exclusive sum of the digit counts. 1 <= width <= 8,
  * shift + width <= key_bits. src and dst must not overlap.

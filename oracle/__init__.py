@@ -24,6 +24,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 STATUS_N, STATUS_L, STATUS_G = 0, 1, 2
+KEY_UNSIGNED, KEY_SIGNED, KEY_FLOAT = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -65,6 +66,15 @@ def lib():
         L.oracle_sort.restype = i32
         L.oracle_sort_segments.argtypes = [vp, vp, vp, vp, i32, sz, u64p, sz, i32, i32, i32]
         L.oracle_sort_segments.restype = i32
+        L.oracle_ordered_bits.argtypes = [ctypes.c_uint64, i32, i32, i32]
+        L.oracle_ordered_bits.restype = ctypes.c_uint64
+        L.oracle_ordered_keys.argtypes = [vp, i32, sz, i32, i32, vp]
+        L.oracle_ordered_keys.restype = i32
+        L.oracle_sort_typed.argtypes = [vp, vp, vp, vp, i32, sz, i32, i32, i32, i32, i32]
+        L.oracle_sort_typed.restype = i32
+        L.oracle_sort_segments_typed.argtypes = [vp, vp, vp, vp, i32, sz, u64p, sz, i32, i32,
+                                                 i32, i32, i32]
+        L.oracle_sort_segments_typed.restype = i32
         L.oracle_pass_status.argtypes = [vp, i32, sz, i32, i32, sz, vp]
         L.oracle_pass_status.restype = i32
         L.oracle_status_pack.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
@@ -153,12 +163,26 @@ def binning_pass(keys: np.ndarray, lo: int, width: int, off_j: np.ndarray,
     return out_k, out_v
 
 
+def ordered_bits(keys: np.ndarray, key_type: int = KEY_UNSIGNED,
+                 descending: bool = False) -> np.ndarray:
+    """The order-preserving transform of raw key bits (uint32/uint64 arrays)."""
+    keys = np.ascontiguousarray(keys)
+    kb = _key_bits(keys)
+    out = np.empty_like(keys)
+    _check(lib().oracle_ordered_keys(_ptr(keys), kb, keys.size, key_type, int(descending),
+                                     _ptr(out)))
+    return out
+
+
 def sort(keys: np.ndarray, vals: np.ndarray | None = None, begin_bit: int = 0,
-         end_bit: int | None = None, d: int = 8, return_passes: bool = False):
+         end_bit: int | None = None, d: int = 8, return_passes: bool = False,
+         key_type: int = KEY_UNSIGNED, descending: bool = False):
     """Stable LSD radix sort of `keys` (and `vals`) by bits [begin_bit, end_bit).
 
-    Returns (keys_out, vals_out) or, with return_passes, also the p per-pass
-    outputs as an array of shape (p, n).
+    Keys are raw uint32/uint64 bits; key_type (unsigned, signed, IEEE float)
+    and descending select the order through oracle_ordered_bits. Returns
+    (keys_out, vals_out) or, with return_passes (unsigned ascending only),
+    also the p per-pass outputs as an array of shape (p, n).
     """
     keys = np.ascontiguousarray(keys)
     kb = _key_bits(keys)
@@ -169,6 +193,12 @@ def sort(keys: np.ndarray, vals: np.ndarray | None = None, begin_bit: int = 0,
     if vals is not None:
         vals = np.ascontiguousarray(vals, dtype=np.uint32)
         out_v = vals.copy()
+    if key_type != KEY_UNSIGNED or descending:
+        if return_passes:
+            raise ValueError("return_passes covers unsigned ascending sorts only")
+        _check(lib().oracle_sort_typed(_ptr(keys), _ptr(vals), _ptr(out_k), _ptr(out_v), kb, n,
+                                       begin_bit, end_bit, d, key_type, int(descending)))
+        return out_k, out_v
     p = num_places(begin_bit, end_bit, d)
     passes = np.zeros((max(p, 0), n), dtype=keys.dtype) if return_passes else None
     _check(lib().oracle_sort(_ptr(keys), _ptr(vals), _ptr(out_k), _ptr(out_v), kb, n,
@@ -179,7 +209,8 @@ def sort(keys: np.ndarray, vals: np.ndarray | None = None, begin_bit: int = 0,
 
 
 def sort_segments(keys: np.ndarray, seg_offsets: np.ndarray, vals: np.ndarray | None = None,
-                  begin_bit: int = 0, end_bit: int | None = None, d: int = 8):
+                  begin_bit: int = 0, end_bit: int | None = None, d: int = 8,
+                  key_type: int = KEY_UNSIGNED, descending: bool = False):
     keys = np.ascontiguousarray(keys)
     kb = _key_bits(keys)
     end_bit = kb if end_bit is None else end_bit
@@ -189,6 +220,12 @@ def sort_segments(keys: np.ndarray, seg_offsets: np.ndarray, vals: np.ndarray | 
     if vals is not None:
         vals = np.ascontiguousarray(vals, dtype=np.uint32)
         out_v = vals.copy()
+    if key_type != KEY_UNSIGNED or descending:
+        _check(lib().oracle_sort_segments_typed(_ptr(keys), _ptr(vals), _ptr(out_k), _ptr(out_v),
+                                                kb, keys.size, _ptr(off), off.size - 1,
+                                                begin_bit, end_bit, d, key_type,
+                                                int(descending)))
+        return out_k, out_v
     _check(lib().oracle_sort_segments(_ptr(keys), _ptr(vals), _ptr(out_k), _ptr(out_v), kb,
                                       keys.size, _ptr(off), off.size - 1, begin_bit, end_bit,
                                       d))

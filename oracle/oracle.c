@@ -221,6 +221,77 @@ int oracle_sort(const void *keys_in, const uint32_t *vals_in, void *keys_out,
 }
 
 /*
+ * Key order (Section 3, binning kernel: signed and floating-point keys are
+ * ranked after a magnitude-preserving conversion to unsigned integers).
+ * key_type 0: unsigned, unchanged. 1: two's complement; adding 2^(w-1)
+ * modulo 2^w maps [-2^(w-1), 2^(w-1)) onto [0, 2^w) in order, which is
+ * flipping the sign bit. 2: IEEE 754; a value with the sign bit clear moves
+ * above every value with it set (sign bit flipped), and among negative values
+ * a larger magnitude must come first, so all bits are flipped. descending:
+ * the result is complemented, reversing the order.
+ */
+uint64_t oracle_ordered_bits(uint64_t key, int key_bits, int key_type, int descending)
+{
+    uint64_t all = key_bits == 64 ? ~(uint64_t)0 : (uint64_t)0xFFFFFFFFu;
+    uint64_t top = (uint64_t)1 << (key_bits - 1);
+    uint64_t k = key & all;
+    if (key_type == 1) {
+        k ^= top;
+    } else if (key_type == 2) {
+        if (k & top) k = ~k & all;
+        else k ^= top;
+    }
+    if (descending) k = ~k & all;
+    return k;
+}
+
+int oracle_ordered_keys(const void *keys, int key_bits, size_t n, int key_type, int descending,
+                        void *out)
+{
+    if (key_bits != 32 && key_bits != 64) return ORACLE_EINVAL;
+    if (key_type < 0 || key_type > 2) return ORACLE_EINVAL;
+    for (size_t i = 0; i < n; i++)
+        store_key(out, key_bits, i,
+                  oracle_ordered_bits(load_key(keys, key_bits, i), key_bits, key_type,
+                                      descending));
+    return ORACLE_OK;
+}
+
+/*
+ * Stable sort of keys of any type and direction: the plain sort of the
+ * ordered bits (oracle_sort), carrying each key's input index as its value,
+ * then a gather of the original keys and values by those indices. Bits
+ * [begin_bit, end_bit) are those of the ordered key.
+ */
+int oracle_sort_typed(const void *keys_in, const uint32_t *vals_in, void *keys_out,
+                      uint32_t *vals_out, int key_bits, size_t n, int begin_bit, int end_bit,
+                      int d, int key_type, int descending)
+{
+    int rc = check_args(key_bits, begin_bit, end_bit, d);
+    if (rc) return rc;
+    if (key_type < 0 || key_type > 2 || n > 0xFFFFFFFFu) return ORACLE_EINVAL;
+    if (n == 0) return ORACLE_OK;
+    size_t kb = (size_t)key_bits / 8;
+    void *t = malloc(kb * n), *t_out = malloc(kb * n);
+    uint32_t *idx = (uint32_t *)malloc(4 * n), *idx_out = (uint32_t *)malloc(4 * n);
+    if (!t || !t_out || !idx || !idx_out) {
+        free(t); free(t_out); free(idx); free(idx_out);
+        return ORACLE_ENOMEM;
+    }
+    oracle_ordered_keys(keys_in, key_bits, n, key_type, descending, t);
+    for (size_t i = 0; i < n; i++) idx[i] = (uint32_t)i;
+    rc = oracle_sort(t, idx, t_out, idx_out, key_bits, n, begin_bit, end_bit, d, NULL);
+    if (rc == ORACLE_OK) {
+        for (size_t i = 0; i < n; i++) {
+            store_key(keys_out, key_bits, i, load_key(keys_in, key_bits, idx_out[i]));
+            if (vals_in && vals_out) vals_out[i] = vals_in[idx_out[i]];
+        }
+    }
+    free(t); free(t_out); free(idx); free(idx_out);
+    return rc;
+}
+
+/*
  * Segmented sort: the same stable sort applied independently to every
  * segment [seg_off[s], seg_off[s+1]). Offsets must be non-decreasing, start at
  * 0 and end at n. This form is not in the paper; its definition is the
@@ -256,6 +327,30 @@ int oracle_sort_segments(const void *keys_in, const uint32_t *vals_in, void *key
  * modulo 2^30 as the 30-bit field stores it; callers keep n below 2^30.
  * status[t * 2^width + v] for tile t and digit v.
  */
+/* Segmented sort of keys of any type and direction: oracle_sort_typed per
+ * segment. */
+int oracle_sort_segments_typed(const void *keys_in, const uint32_t *vals_in, void *keys_out,
+                               uint32_t *vals_out, int key_bits, size_t n,
+                               const uint64_t *seg_off, size_t num_segments, int begin_bit,
+                               int end_bit, int d, int key_type, int descending)
+{
+    int rc = check_args(key_bits, begin_bit, end_bit, d);
+    if (rc) return rc;
+    size_t kb = (size_t)key_bits / 8;
+    if (num_segments == 0) return n == 0 ? ORACLE_OK : ORACLE_EINVAL;
+    if (seg_off[0] != 0 || seg_off[num_segments] != n) return ORACLE_EINVAL;
+    for (size_t s = 0; s < num_segments; s++)
+        if (seg_off[s + 1] < seg_off[s]) return ORACLE_EINVAL;
+    for (size_t s = 0; s < num_segments; s++) {
+        size_t a = (size_t)seg_off[s], len = (size_t)(seg_off[s + 1] - seg_off[s]);
+        rc = oracle_sort_typed((const char *)keys_in + a * kb, vals_in ? vals_in + a : NULL,
+                               (char *)keys_out + a * kb, vals_out ? vals_out + a : NULL,
+                               key_bits, len, begin_bit, end_bit, d, key_type, descending);
+        if (rc) return rc;
+    }
+    return ORACLE_OK;
+}
+
 int oracle_pass_status(const void *src_keys, int key_bits, size_t n, int lo, int width,
                        size_t tile, uint32_t *status)
 {

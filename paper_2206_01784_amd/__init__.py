@@ -49,6 +49,7 @@ class Config(ctypes.Structure):
                 ("items_per_thread", ctypes.c_int), ("hist_blocks_per_cu", ctypes.c_int),
                 ("rank_algorithm", ctypes.c_int), ("segment_limits", ctypes.c_int * 3),
                 ("segment_streams", ctypes.c_int), ("algorithm", ctypes.c_int),
+                ("key_type", ctypes.c_int), ("descending", ctypes.c_int),
                 ("trace", ctypes.POINTER(Trace))]
 
 
@@ -98,14 +99,16 @@ def _check(code: int):
 
 RANK_DEFAULT, RANK_BALLOT, RANK_PRESENCE, RANK_ATOMIC = 0, 1, 2, 3
 ALGORITHM_ONESWEEP, ALGORITHM_REDUCE_THEN_SCAN = 0, 1
+KEY_UNSIGNED, KEY_SIGNED, KEY_FLOAT = 0, 1, 2
 
 
 def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,
                 digit_bits: int = 0, rank_algorithm: int = 0, segment_limits=(0, 0, 0),
-                segment_streams: int = 0, algorithm: int = 0,
-                trace: Trace | None = None) -> Config:
+                segment_streams: int = 0, algorithm: int = 0, key_type: int = 0,
+                descending: bool = False, trace: Trace | None = None) -> Config:
     c = Config(digit_bits, block_threads, items_per_thread, hist_blocks_per_cu, rank_algorithm,
-               (ctypes.c_int * 3)(*segment_limits), segment_streams, algorithm, None)
+               (ctypes.c_int * 3)(*segment_limits), segment_streams, algorithm, key_type,
+               int(descending), None)
     if trace is not None:
         c.trace = ctypes.pointer(trace)
     return c
@@ -115,12 +118,33 @@ def _cfg_ptr(cfg):
     return None if cfg is None else ctypes.byref(cfg)
 
 
+_KEY_DTYPES = {
+    torch.uint32: (32, KEY_UNSIGNED), torch.uint64: (64, KEY_UNSIGNED),
+    torch.int32: (32, KEY_SIGNED), torch.int64: (64, KEY_SIGNED),
+    torch.float32: (32, KEY_FLOAT), torch.float64: (64, KEY_FLOAT),
+}
+
+
 def _key_bits(t: torch.Tensor) -> int:
-    if t.dtype == torch.uint32:
-        return 32
-    if t.dtype == torch.uint64:
-        return 64
-    raise TypeError(f"keys must be torch.uint32 or torch.uint64, got {t.dtype}")
+    if t.dtype not in _KEY_DTYPES:
+        raise TypeError(f"keys must be torch.uint32/uint64/int32/int64/float32/float64, "
+                        f"got {t.dtype}")
+    return _KEY_DTYPES[t.dtype][0]
+
+
+def _ordered_config(config: Config | None, keys: torch.Tensor, descending: bool):
+    """The config with the key type of a signed or floating-point dtype and
+    the requested direction (a copy; the caller's config is left as it is).
+    Unsigned tensors keep the config's key_type, so raw bits of signed or
+    floating-point keys can be sorted through it."""
+    key_type = _KEY_DTYPES[keys.dtype][1] if keys.dtype in _KEY_DTYPES else KEY_UNSIGNED
+    if key_type == KEY_UNSIGNED and not descending:
+        return config
+    c = Config() if config is None else Config.from_buffer_copy(config)
+    if key_type != KEY_UNSIGNED:
+        c.key_type = key_type
+    c.descending = int(bool(descending) or bool(c.descending))
+    return c
 
 
 def _dev_ptr(t: torch.Tensor | None):
@@ -169,9 +193,14 @@ def _temp(temp, need, device):
 
 def sort_keys(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
               out: torch.Tensor | None = None, temp: torch.Tensor | None = None,
-              config: Config | None = None, stream=None) -> torch.Tensor:
-    """Stable ascending sort of uint32/uint64 keys by bits [begin_bit, end_bit)."""
+              config: Config | None = None, stream=None, descending: bool = False) -> torch.Tensor:
+    """Stable sort of keys by bits [begin_bit, end_bit) of their ordered bits.
+
+    uint32/uint64 keys sort as unsigned integers, int32/int64 as signed,
+    float32/float64 as IEEE 754 values (-NaN < -inf < -0 < +0 < +inf < +NaN).
+    """
     kb = _key_bits(keys)
+    config = _ordered_config(config, keys, descending)
     end_bit = kb if end_bit is None else end_bit
     n = keys.numel()
     if out is None:
@@ -188,9 +217,11 @@ def sort_keys(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None
 def sort_pairs(keys: torch.Tensor, values: torch.Tensor, begin_bit: int = 0,
                end_bit: int | None = None, keys_out: torch.Tensor | None = None,
                values_out: torch.Tensor | None = None, temp: torch.Tensor | None = None,
-               config: Config | None = None, stream=None):
-    """Stable sort of (key, uint32 value) pairs; returns (keys_out, values_out)."""
+               config: Config | None = None, stream=None, descending: bool = False):
+    """Stable sort of (key, uint32 value) pairs (key types as in sort_keys);
+    returns (keys_out, values_out)."""
     kb = _key_bits(keys)
+    config = _ordered_config(config, keys, descending)
     if values.dtype != torch.uint32:
         raise TypeError("values must be torch.uint32")
     if values.numel() != keys.numel():
@@ -210,9 +241,11 @@ def sort_pairs(keys: torch.Tensor, values: torch.Tensor, begin_bit: int = 0,
 
 def histogram(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
               out: torch.Tensor | None = None, config: Config | None = None,
-              stream=None) -> torch.Tensor:
-    """Phase 1 alone: uint32 digit counts of every 8-bit place, shape (p, 256)."""
+              stream=None, descending: bool = False) -> torch.Tensor:
+    """Phase 1 alone: uint32 digit counts of every 8-bit place of the ordered
+    key bits, shape (p, 256)."""
     kb = _key_bits(keys)
+    config = _ordered_config(config, keys, descending)
     end_bit = kb if end_bit is None else end_bit
     p = (end_bit - begin_bit + RADIX_BITS - 1) // RADIX_BITS
     if out is None:
@@ -236,13 +269,15 @@ def binning_pass_temp_bytes(n: int, key_bits: int = 32, has_values: bool = False
 def binning_pass(src: torch.Tensor, bin_offsets: torch.Tensor, shift: int, width: int = 8,
                  dst: torch.Tensor | None = None, src_values: torch.Tensor | None = None,
                  dst_values: torch.Tensor | None = None, temp: torch.Tensor | None = None,
-                 config: Config | None = None, stream=None):
-    """Phase 3, one iteration: stable scatter of src by digit (key >> shift) & (2^width - 1).
+                 config: Config | None = None, stream=None, descending: bool = False):
+    """Phase 3, one iteration: stable scatter of src by digit
+    (ordered bits >> shift) & (2^width - 1), key types as in sort_keys.
 
     Returns (dst, dst_values, temp); temp holds the tile counter and the
     chained-scan status words (see onesweep_binning_pass in include/onesweep.h).
     """
     kb = _key_bits(src)
+    config = _ordered_config(config, src, descending)
     if bin_offsets.dtype != torch.uint32 or bin_offsets.numel() != RADIX:
         raise ValueError("bin_offsets must be 256 uint32")
     n = src.numel()
@@ -276,8 +311,10 @@ def sort_segments_temp_bytes(n: int, num_segments: int, key_bits: int = 32,
 def sort_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tensor | None = None,
                   begin_bit: int = 0, end_bit: int | None = None,
                   keys_out: torch.Tensor | None = None, values_out: torch.Tensor | None = None,
-                  temp: torch.Tensor | None = None, config: Config | None = None, stream=None):
-    """Stable sort of every segment [offsets[s], offsets[s+1]) on its own.
+                  temp: torch.Tensor | None = None, config: Config | None = None, stream=None,
+                  descending: bool = False):
+    """Stable sort of every segment [offsets[s], offsets[s+1]) on its own
+    (key types as in sort_keys).
 
     offsets: uint32 device tensor of num_segments + 1 entries (0 first, n
     last, non-decreasing). Returns keys_out, or (keys_out, values_out) when
@@ -285,6 +322,7 @@ def sort_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tenso
     device found the offsets invalid (then nothing was written), else 0.
     """
     kb = _key_bits(keys)
+    config = _ordered_config(config, keys, descending)
     if offsets.dtype != torch.uint32:
         raise TypeError("offsets must be torch.uint32")
     if offsets.numel() < 1:

@@ -70,8 +70,26 @@ struct Resolved {
   BinningShape shape;
   int hist_blocks_per_cu;
   int algorithm;  // onesweep_algorithm_t
+  KeyOrder order;
   onesweep_trace_t *trace;
 };
+
+// Constants of the order transform for a key width, key type and direction;
+// `pad` is the key whose transformed bits are all ones (the largest digit at
+// every place), which fills the lanes past the end of a tile.
+KeyOrder key_order(int key_bits, int key_type, bool descending) {
+  const uint64_t all = key_bits == 64 ? ~uint64_t(0) : uint64_t(0xFFFFFFFFu);
+  const uint64_t top = uint64_t(1) << (key_bits - 1);
+  KeyOrder o{};
+  o.sign = key_type != ONESWEEP_KEY_UNSIGNED ? top : 0u;
+  o.negative = key_type == ONESWEEP_KEY_FLOAT ? all : 0u;
+  o.invert = descending ? all : 0u;
+  if (!descending)
+    o.pad = key_type == ONESWEEP_KEY_UNSIGNED ? all : (all ^ top);
+  else
+    o.pad = key_type == ONESWEEP_KEY_UNSIGNED ? 0u : (key_type == ONESWEEP_KEY_SIGNED ? top : all);
+  return o;
+}
 
 // Which entry point resolves: whole plain sorts offer both algorithms, the
 // segmented sort has its own binning shapes, the rest take Onesweep's.
@@ -82,6 +100,7 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
   r->shape = binning_default_shape(key_bits, has_values, n);
   r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
   r->algorithm = ONESWEEP_ALGORITHM_ONESWEEP;
+  r->order = key_order(key_bits, ONESWEEP_KEY_UNSIGNED, false);
   r->trace = nullptr;
   if (cfg != nullptr) {
     if (cfg->digit_bits != 0 && cfg->digit_bits != kRadixBits)
@@ -104,6 +123,12 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
                   "algorithm %d: reduce-then-scan is offered by whole plain sorts only",
                   cfg->algorithm);
     r->algorithm = cfg->algorithm;
+    if (cfg->key_type < ONESWEEP_KEY_UNSIGNED || cfg->key_type > ONESWEEP_KEY_FLOAT)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "key_type %d not 0, 1 or 2", cfg->key_type);
+    if (cfg->descending != 0 && cfg->descending != 1)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "descending %d not 0 or 1", cfg->descending);
+    if (key_bits == 32 || key_bits == 64)
+      r->order = key_order(key_bits, cfg->key_type, cfg->descending != 0);
     r->trace = cfg->trace;
     if (r->trace && (r->trace->capacity < 0 || r->trace->capacity > ONESWEEP_TRACE_MAX ||
                      (r->trace->capacity > 0 && r->trace->events == nullptr)))
@@ -296,7 +321,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
                   launch_fill_zero(temp + L.hist, L.zero_end - L.hist, stream_grid, stream));
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
                   launch_histogram(key_bits, keys_in, hist, static_cast<uint32_t>(n), begin_bit,
-                                   end_bit, places,
+                                   end_bit, places, rc.order,
                                    static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), stream));
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_SCAN, "scan",
                   launch_scan(hist, offsets, plan, places, static_cast<uint32_t>(n), alias,
@@ -314,6 +339,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
         UpsweepArgs<uint32_t> u{};
         for (int b = 0; b < 3; ++b) u.keys[b] = static_cast<uint32_t *>(ca.keys[b]);
         u.plan = plan;
+        u.order = rc.order;
         u.counts = table;
         u.n = static_cast<uint32_t>(n);
         u.place = j;
@@ -331,6 +357,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
       a.status = table;
       a.tile_counter = counters + j;
       a.plan = plan;
+      a.order = rc.order;
       a.n = static_cast<uint32_t>(n);
       a.place = j;
       a.shift = lo;
@@ -341,6 +368,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
         UpsweepArgs<uint64_t> u{};
         for (int b = 0; b < 3; ++b) u.keys[b] = static_cast<uint64_t *>(ca.keys[b]);
         u.plan = plan;
+        u.order = rc.order;
         u.counts = table;
         u.n = static_cast<uint32_t>(n);
         u.place = j;
@@ -358,6 +386,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
       a.status = table;
       a.tile_counter = counters + j;
       a.plan = plan;
+      a.order = rc.order;
       a.n = static_cast<uint32_t>(n);
       a.place = j;
       a.shift = lo;
@@ -644,6 +673,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
     la.begin_bit = begin_bit;
     la.end_bit = end_bit;
     la.places = places;
+    la.order = rc.order;
     const uint32_t grid =
         std::min<uint32_t>(L.capacity[c], static_cast<uint32_t>(cus) * static_cast<uint32_t>(per_cu));
     ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_LDS_SORT, "lds sort",
@@ -671,6 +701,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   ha.begin_bit = begin_bit;
   ha.end_bit = end_bit;
   ha.places = places;
+  ha.order = rc.order;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "segment histogram",
                   launch_segment_histogram(key_bits, ha, std::min(L.max_tiles, stream_grid),
                                            stream));
@@ -709,6 +740,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
       a.status = status + j * L.status_words_per_place;
       a.tile_counter = counters + j;
       a.seg = seg;
+      a.order = rc.order;
       a.n = static_cast<uint32_t>(n);
       a.place = j;
       a.shift = lo;
@@ -724,6 +756,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
       a.status = status + j * L.status_words_per_place;
       a.tile_counter = counters + j;
       a.seg = seg;
+      a.order = rc.order;
       a.n = static_cast<uint32_t>(n);
       a.place = j;
       a.shift = lo;
@@ -803,7 +836,7 @@ onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits,
   if (n == 0) return ONESWEEP_SUCCESS;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
                   launch_histogram(key_bits, d_keys, d_hist, static_cast<uint32_t>(n), begin_bit,
-                                   end_bit, places,
+                                   end_bit, places, rc.order,
                                    static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), s));
   return ONESWEEP_SUCCESS;
 }
@@ -871,6 +904,7 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.status = status;
     a.tile_counter = counter;
     a.plan = nullptr;
+    a.order = rc.order;
     a.n = static_cast<uint32_t>(n);
     a.place = 0;
     a.shift = shift;
@@ -887,6 +921,7 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.status = status;
     a.tile_counter = counter;
     a.plan = nullptr;
+    a.order = rc.order;
     a.n = static_cast<uint32_t>(n);
     a.place = 0;
     a.shift = shift;

@@ -167,9 +167,10 @@ __global__ void __launch_bounds__(kBlock)
   const uint32_t tile_end = tile_base + tile_count;
   const bool full = tile_count == static_cast<uint32_t>(kTile);
 
-  // 1. Load. Lanes past the end get an all-ones key: its digit is the
-  // largest one the place can hold and it ranks after every real key, so the
-  // padding occupies the last tile positions and is never written out.
+  // 1. Load. Lanes past the end get the key whose ordered bits are all ones:
+  // its digit is the largest one the place can hold and it ranks after every
+  // real key, so the padding occupies the last tile positions and is never
+  // written out.
   K key[kIpt];
   const uint32_t wave_base = tile_base + wave * kWaveItems + lane;
   if (full) {
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t idx = wave_base + i * kWave;
-      key[i] = idx < tile_end ? src[idx] : static_cast<K>(~static_cast<K>(0));
+      key[i] = idx < tile_end ? src[idx] : static_cast<K>(a.order.pad);
     }
   }
 
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(kBlock)
         pos[r] += __shfl(prior[r], static_cast<int>(leader[r]), kWave);
       }
       if (i >= kIpt) continue;
-      const uint32_t d = digit_of(key[i], shift, mask);
+      const uint32_t d = digit_of(key[i], shift, mask, a.order);
       uint32_t peers_lo = ~0u, peers_hi = ~0u;
 #pragma unroll
       for (int b = 0; b < kRadixBits; ++b) {
@@ -219,7 +220,7 @@ __global__ void __launch_bounds__(kBlock)
   } else {
 #pragma unroll
   for (int i = 0; i < kIpt; ++i) {
-    const uint32_t d = digit_of(key[i], shift, mask);
+    const uint32_t d = digit_of(key[i], shift, mask, a.order);
     const uint32_t e = wave_table + d * kEntryWords;
     uint32_t peers_lo, peers_hi;
     if constexpr (kRank == kRankPresence) {
@@ -295,7 +296,7 @@ __global__ void __launch_bounds__(kBlock)
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kIpt; ++i)
-    pos[i] += s_rank[wave_table + digit_of(key[i], shift, mask) * kEntryWords];
+    pos[i] += s_rank[wave_table + digit_of(key[i], shift, mask, a.order) * kEntryWords];
   __syncthreads();  // the rank tables are dead; the region now holds the tile
   const uint32_t uniform = kShortCircuit ? s_uniform : 0u;
 
@@ -391,7 +392,7 @@ __global__ void __launch_bounds__(kBlock)
     const uint32_t q = i * kBlock + tid;
     if (full || q < tile_count) {
       const K k = s_keys[q];
-      const uint32_t g = s_gbase[digit_of(k, shift, mask)] + q;
+      const uint32_t g = s_gbase[digit_of(k, shift, mask, a.order)] + q;
       if (!kCheckedStores || g < n) dst[g] = k;
       if constexpr (kVals) dst_idx[i] = g;
     }

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace onesweep {
 
 constexpr int kRadixBits = 8;
@@ -22,6 +24,19 @@ constexpr uint32_t kFlagG = 2u << 30;
 
 // Buffer ids used by the pass plan.
 enum : uint32_t { kBufIn = 0, kBufOut = 1, kBufTmp = 2, kNoBuffer = 3 };
+
+// Order of the key bits. Signed and floating-point keys are ranked through a
+// magnitude-preserving transform onto unsigned order (Section 3, binning
+// kernel): the sign bit flips, and negative floating-point keys flip every
+// bit; descending order complements the result. The transform only decides
+// digits: keys are read and written unchanged. 32-bit keys use the low halves
+// of the fields.
+struct KeyOrder {
+  uint64_t sign;      // the top key bit for signed and floating-point keys, else 0
+  uint64_t negative;  // all ones for floating-point keys, else 0
+  uint64_t invert;    // all ones for descending order, else 0
+  uint64_t pad;       // the key whose transformed bits are all ones (padding lanes)
+};
 
 // The pass plan is computed on the device by the scan kernel from the exact
 // histograms, so the host never synchronises to learn which passes run:
@@ -74,6 +89,7 @@ struct BinningArgs {
   uint32_t *tile_counter;      // dynamic tile ids of this place
   const PassPlan *plan;        // NULL: run unconditionally in -> out
   SegmentTiles seg;            // segmented sort only
+  KeyOrder order;
   uint32_t n;
   int place;
   int shift;
@@ -88,6 +104,7 @@ struct HistogramArgs {
   int begin_bit;
   int end_bit;
   int places;
+  KeyOrder order;
 };
 
 // Agent-scope atomics: successive tiles usually run on different XCDs, whose
@@ -113,8 +130,31 @@ __device__ __forceinline__ uint32_t count_below(uint64_t mask) {
 }
 
 template <typename K>
+__device__ __forceinline__ K ordered_bits(K key, const KeyOrder &o) {
+  using S = typename std::make_signed<K>::type;
+  const K neg = static_cast<K>(static_cast<S>(key) >> (8 * sizeof(K) - 1));
+  return key ^ ((neg & static_cast<K>(o.negative)) | static_cast<K>(o.sign)) ^
+         static_cast<K>(o.invert);
+}
+
+// Inverse of ordered_bits: u is the transformed key with the direction
+// undone; a floating-point key was negative exactly when u's top bit is 0.
+template <typename K>
+__device__ __forceinline__ K original_bits(K t, const KeyOrder &o) {
+  using S = typename std::make_signed<K>::type;
+  const K u = t ^ static_cast<K>(o.invert);
+  const K was_negative = ~static_cast<K>(static_cast<S>(u) >> (8 * sizeof(K) - 1));
+  return u ^ ((was_negative & static_cast<K>(o.negative)) | static_cast<K>(o.sign));
+}
+
+template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
   return static_cast<uint32_t>(key >> shift) & mask;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask, const KeyOrder &o) {
+  return digit_of(ordered_bits(key, o), shift, mask);
 }
 
 // Inclusive sum over the lanes of a wavefront.

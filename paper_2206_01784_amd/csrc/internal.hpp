@@ -57,6 +57,7 @@ struct UpsweepArgs {
   int place;
   int shift;
   int width;
+  KeyOrder order;
 };
 bool upsweep_shape_supported(int key_bits, int block, int ipt);
 hipError_t launch_upsweep(int key_bits, int block, int ipt, const void *args, uint32_t tiles,
@@ -67,8 +68,8 @@ hipError_t launch_tile_scan(uint32_t *counts, uint32_t tiles, const PassPlan *pl
 // Histogram of all places (phase 1), persistent tile-cyclic grid.
 constexpr int kHistBlock = 256;
 hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint32_t n,
-                            int begin_bit, int end_bit, int places, uint32_t grid,
-                            hipStream_t stream);
+                            int begin_bit, int end_bit, int places, const KeyOrder &order,
+                            uint32_t grid, hipStream_t stream);
 
 // Exclusive sums of every place's histogram and the pass plan (phase 2).
 hipError_t launch_scan(const uint32_t *hist, uint32_t *offsets, PassPlan *plan, int places,
@@ -126,6 +127,7 @@ struct SegmentHistArgs {
   int begin_bit;
   int end_bit;
   int places;
+  KeyOrder order;
 };
 hipError_t launch_segment_histogram(int key_bits, const SegmentHistArgs &a, uint32_t grid,
                                     hipStream_t stream);
@@ -155,6 +157,7 @@ struct LdsSortArgs {
   int begin_bit;
   int end_bit;
   int places;
+  KeyOrder order;
 };
 int lds_class_capacity(int cls);
 int lds_class_block(int cls);

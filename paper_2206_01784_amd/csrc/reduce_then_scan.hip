@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(kBlock) upsweep_kernel(UpsweepArgs<K> a) {
     for (int i = 0; i < kIpt; ++i) key[i] = src[wb + i * kWave];
 #pragma unroll
     for (int i = 0; i < kIpt; ++i)
-      __hip_atomic_fetch_add(&mine[digit_of(key[i], shift, mask) * kCopies], 1u,
+      __hip_atomic_fetch_add(&mine[digit_of(key[i], shift, mask, a.order) * kCopies], 1u,
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   } else {
     const uint32_t end = base + count;
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(kBlock) upsweep_kernel(UpsweepArgs<K> a) {
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t idx = wb + i * kWave;
       if (idx < end)
-        __hip_atomic_fetch_add(&mine[digit_of(src[idx], shift, mask) * kCopies], 1u,
+        __hip_atomic_fetch_add(&mine[digit_of(src[idx], shift, mask, a.order) * kCopies], 1u,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }

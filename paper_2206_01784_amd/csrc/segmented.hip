@@ -183,10 +183,11 @@ __global__ void __launch_bounds__(256) segment_histogram_kernel(SegmentHistArgs 
 #pragma unroll
       for (int b = 0; b < kBatch; ++b) {
         if (base + b * 256 + tid >= info.y) continue;
+        const K o = ordered_bits(k[b], a.order);
 #pragma unroll
         for (int j = 0; j < kMaxP; ++j)
           if (j < places)
-            atomicAdd(&my_hist[(j * kRadix + (static_cast<uint32_t>(k[b] >> shifts[j]) & masks[j])) *
+            atomicAdd(&my_hist[(j * kRadix + (static_cast<uint32_t>(o >> shifts[j]) & masks[j])) *
                                kCopies],
                       1u);
       }
@@ -280,7 +281,8 @@ hipError_t launch_segment_copy(const SegmentCopyArgs &a, uint32_t grid, hipStrea
 // positions in LDS and read them back in slot order. Batches of 64 slots
 // that start past the segment's end take no part; the last partial batch is
 // padded with all-ones keys, which rank after every real key and so stay in
-// the slots past the end.
+// the slots past the end. Keys are held as their ordered bits (signed,
+// floating-point and descending orders) from load to store.
 // The 1024-thread class with 32-bit keys is held to 64 registers so two
 // workgroups fit a CU.
 template <typename K, int kBlock>
@@ -343,7 +345,8 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t q = wave_first + i * kWave + lane;
-      key[i] = q < len ? kin[lo + q] : static_cast<K>(~static_cast<K>(0));
+      // keys are held as their ordered bits from load to store
+      key[i] = q < len ? ordered_bits(kin[lo + q], a.order) : static_cast<K>(~static_cast<K>(0));
       if constexpr (kVals) val[i] = q < len ? a.vals_in[lo + q] : 0u;
     }
     for (int j = 0; j < a.places; ++j) {
@@ -419,7 +422,7 @@ __global__ void __launch_bounds__(kBlock)
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t q = wave_first + i * kWave + lane;
       if (q < len) {
-        kout[lo + q] = key[i];
+        kout[lo + q] = original_bits(key[i], a.order);
         if constexpr (kVals) a.vals_out[lo + q] = val[i];
       }
     }

@@ -42,10 +42,11 @@ __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
   __syncthreads();
 
   auto count_key = [&](K k) {
+    const K t = ordered_bits(k, a.order);
 #pragma unroll
     for (int j = 0; j < kMaxP; ++j) {
       if (j < places) {
-        const uint32_t d = static_cast<uint32_t>(k >> shifts[j]) & masks[j];
+        const uint32_t d = static_cast<uint32_t>(t >> shifts[j]) & masks[j];
         atomicAdd(&my_hist[(j * kRadix + d) * kCopies], 1u);
       }
     }
@@ -89,16 +90,16 @@ constexpr int kHistVec = 4;     // uint4 loads per thread per tile
 constexpr int kHistCopies = 8;  // interleaved LDS copies per counter
 
 hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint32_t n,
-                            int begin_bit, int end_bit, int places, uint32_t grid,
-                            hipStream_t stream) {
+                            int begin_bit, int end_bit, int places, const KeyOrder &order,
+                            uint32_t grid, hipStream_t stream) {
   if (key_bits == 32) {
     HistogramArgs<uint32_t> a{static_cast<const uint32_t *>(keys), hist, n, begin_bit, end_bit,
-                              places};
+                              places, order};
     hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies>),
                        dim3(grid), dim3(kHistBlock), 0, stream, a);
   } else {
     HistogramArgs<uint64_t> a{static_cast<const uint64_t *>(keys), hist, n, begin_bit, end_bit,
-                              places};
+                              places, order};
     hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies>),
                        dim3(grid), dim3(kHistBlock), 0, stream, a);
   }

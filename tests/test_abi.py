@@ -125,6 +125,24 @@ def test_reduce_then_scan_config_validation_needs_no_gpu():
     assert rc == ow.ERROR_INVALID_VALUE
 
 
+def test_key_type_and_direction_validation_needs_no_gpu():
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    size = ctypes.c_size_t(0)
+    for kwargs in (dict(key_type=3), dict(key_type=-1), dict(descending=2)):
+        cfg = ow.make_config(**kwargs)
+        if "descending" in kwargs:
+            cfg.descending = kwargs["descending"]
+        rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
+                                    ctypes.byref(cfg), None)
+        assert rc == ow.ERROR_INVALID_VALUE, kwargs
+    for kt in (ow.KEY_UNSIGNED, ow.KEY_SIGNED, ow.KEY_FLOAT):
+        for desc in (False, True):
+            cfg = ow.make_config(key_type=kt, descending=desc)
+            assert ow.sort_temp_bytes(1000, 64, True, config=cfg) == \
+                ow.sort_temp_bytes(1000, 64, True)
+
+
 def test_insufficient_temp_and_null_pointers():
     import paper_2206_01784_amd as ow
     lib = ow.library()

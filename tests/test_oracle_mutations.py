@@ -38,6 +38,15 @@ MUTANTS = {
                            "if (src_vals) dst_vals[i] = src_vals[i];"),
     "digit_mask_one_bit_short": ("return (key >> lo) & ((1ull << width) - 1ull);",
                                  "return (key >> lo) & ((1ull << width) - 2ull);"),
+    "signed_sign_bit_kept": ("    if (key_type == 1) {\n        k ^= top;",
+                             "    if (key_type == 1) {\n        k ^= 0;"),
+    "negative_floats_flip_sign_only": ("        if (k & top) k = ~k & all;",
+                                       "        if (k & top) k ^= top;"),
+    "positive_floats_unflipped": ("        else k ^= top;", "        else k ^= 0;"),
+    "descending_ignored": ("    if (descending) k = ~k & all;", "    if (descending) k = k & all;"),
+    "typed_gather_keeps_input_order": (
+        "store_key(keys_out, key_bits, i, load_key(keys_in, key_bits, idx_out[i]));",
+        "store_key(keys_out, key_bits, i, load_key(keys_in, key_bits, i));"),
 }
 
 

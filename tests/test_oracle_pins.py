@@ -290,3 +290,116 @@ def test_pass_status_invariants():
         assert np.array_equal(vals[t] - prev, cnt)
         prev = vals[t]
     assert np.array_equal(vals[-1], np.bincount(dig, minlength=1 << width))
+
+
+# ---------------------------------------------------------------- key order
+
+def _float_class_key(bits: int, kb: int):
+    """Rank of an IEEE 754 bit pattern in the order the sort promises
+    (-NaN < -inf < negative < -0 < +0 < positive < +inf < +NaN, NaNs by their
+    magnitude bits), computed from the decoded value, not from the bit
+    transform under test."""
+    ftype, itype = (np.float32, np.uint32) if kb == 32 else (np.float64, np.uint64)
+    x = float(np.array([bits], dtype=itype).view(ftype)[0])
+    negative = bits >> (kb - 1)
+    magnitude = bits & ((1 << (kb - 1)) - 1)
+    if x != x:
+        return (0, -magnitude) if negative else (7, magnitude)
+    if x == float("-inf"):
+        return (1, 0)
+    if x == float("inf"):
+        return (6, 0)
+    if x == 0.0:
+        return (3, 0) if negative else (4, 0)
+    return (2, x) if x < 0 else (5, x)
+
+
+SPECIAL_F32 = [0x00000000, 0x80000000, 0x7F800000, 0xFF800000, 0x7FC00000, 0xFFC00000,
+               0x7F800001, 0xFF800001, 0x00000001, 0x80000001, 0x3F800000, 0xBF800000,
+               0x7F7FFFFF, 0xFF7FFFFF, 0x00800000, 0x80800000]
+SPECIAL_F64 = [0x0, 0x8000000000000000, 0x7FF0000000000000, 0xFFF0000000000000,
+               0x7FF8000000000000, 0xFFF8000000000000, 0x7FF0000000000001,
+               0xFFF0000000000001, 0x1, 0x8000000000000001, 0x3FF0000000000000,
+               0xBFF0000000000000, 0x7FEFFFFFFFFFFFFF, 0xFFEFFFFFFFFFFFFF]
+
+
+def test_signed_ordered_bits_closed_form():
+    """Two's complement: the ordered bits are x + 2^(w-1) as an unsigned number."""
+    for kb, st, ut in ((32, np.int32, np.uint32), (64, np.int64, np.uint64)):
+        x = np.array([-(1 << (kb - 1)), -2, -1, 0, 1, 7, (1 << (kb - 1)) - 1], dtype=st)
+        got = oracle.ordered_bits(x.view(ut), oracle.KEY_SIGNED)
+        want = [int(v) + (1 << (kb - 1)) for v in x]
+        assert [int(g) for g in got] == want
+        desc = oracle.ordered_bits(x.view(ut), oracle.KEY_SIGNED, descending=True)
+        assert [int(g) for g in desc] == [(1 << kb) - 1 - w for w in want]
+
+
+def test_float_ordered_bits_follow_the_total_order():
+    for kb, specials, ut in ((32, SPECIAL_F32, np.uint32), (64, SPECIAL_F64, np.uint64)):
+        ranked = sorted(specials, key=lambda b: _float_class_key(b, kb))
+        got = oracle.ordered_bits(np.array(ranked, dtype=ut), oracle.KEY_FLOAT)
+        assert all(int(a) < int(b) for a, b in zip(got[:-1], got[1:])), kb
+        down = oracle.ordered_bits(np.array(ranked, dtype=ut), oracle.KEY_FLOAT, descending=True)
+        assert all(int(a) > int(b) for a, b in zip(down[:-1], down[1:])), kb
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_signed_sort_matches_numpy(kb):
+    st, ut = (np.int32, np.uint32) if kb == 32 else (np.int64, np.uint64)
+    rng = np.random.default_rng(71)
+    x = rng.integers(-600, 600, 6000).astype(st)  # both signs, many ties
+    x[:4] = [np.iinfo(st).min, np.iinfo(st).max, -1, 0]
+    v = np.arange(x.size, dtype=np.uint32)
+    ko, vo = oracle.sort(x.view(ut), v, key_type=oracle.KEY_SIGNED)
+    order = np.argsort(x, kind="stable")
+    assert np.array_equal(vo, order)
+    assert np.array_equal(ko.view(st), x[order])
+    ko, vo = oracle.sort(x.view(ut), v, key_type=oracle.KEY_SIGNED, descending=True)
+    down = np.argsort(-x.astype(np.float64), kind="stable")  # exact: |x| < 2^53
+    assert np.array_equal(vo, down)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_float_sort_matches_numpy_on_finite_nonzero_values(kb):
+    ft, ut = (np.float32, np.uint32) if kb == 32 else (np.float64, np.uint64)
+    rng = np.random.default_rng(73)
+    ints = rng.integers(1, 400, 5000) * rng.choice([-1, 1], 5000)
+    x = (ints * 0.37).astype(ft) * ft(10.0) ** rng.integers(-3, 4, 5000).astype(ft)
+    v = np.arange(x.size, dtype=np.uint32)
+    ko, vo = oracle.sort(x.view(ut), v, key_type=oracle.KEY_FLOAT)
+    order = np.argsort(x, kind="stable")
+    assert np.array_equal(vo, order)
+    assert np.array_equal(ko, x.view(ut)[order])
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_float_sort_of_special_values_brute_force(kb):
+    specials = SPECIAL_F32 if kb == 32 else SPECIAL_F64
+    ut = np.uint32 if kb == 32 else np.uint64
+    rng = np.random.default_rng(79)
+    bits = np.array([specials[i] for i in rng.integers(0, len(specials), 700)], dtype=ut)
+    v = np.arange(bits.size, dtype=np.uint32)
+    for descending in (False, True):
+        sign = -1 if descending else 1
+        want = sorted(range(bits.size),
+                      key=lambda i: (tuple(sign * c for c in _float_class_key(int(bits[i]), kb)),
+                                     i))
+        ko, vo = oracle.sort(bits, v, key_type=oracle.KEY_FLOAT, descending=descending)
+        assert list(vo) == want, descending
+        assert np.array_equal(ko, bits[want])
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_descending_unsigned_sort_brute_force(kb):
+    ut = np.uint32 if kb == 32 else np.uint64
+    rng = np.random.default_rng(83)
+    k = rng.integers(0, 1 << 20, 3000, dtype=np.uint64).astype(ut) << ut(kb - 20)
+    k[::7] = k[3]  # ties
+    v = np.arange(k.size, dtype=np.uint32)
+    ko, vo = oracle.sort(k, v, descending=True)
+    assert list(vo) == sorted(range(k.size), key=lambda i: (-int(k[i]), i))
+    # a bit range: descending by the field, ties (equal fields) in input order
+    b, e = 3, kb - 9
+    field = lambda i: (int(k[i]) >> b) & ((1 << (e - b)) - 1)  # noqa: E731
+    ko, vo = oracle.sort(k, v, b, e, descending=True)
+    assert list(vo) == sorted(range(k.size), key=lambda i: (-field(i), i))

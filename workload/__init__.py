@@ -196,6 +196,40 @@ def runs(seed: int, n: int, key_bits: int = 32, run: int = 1 << 16, low_bits: in
     return (np.repeat(high, run)[:n] & ~low) | (w & low)
 
 
+def signed_ints(seed: int, n: int, key_bits: int = 32, span_bits: int = 12) -> np.ndarray:
+    """Raw bits of two's-complement integers in [-2^(span_bits-1), 2^(span_bits-1)):
+    the top span_bits of a uniform word, sign-extended (ties and both signs)."""
+    w = uniform(seed, n, key_bits)
+    st = np.int32 if key_bits == 32 else np.int64
+    return (w.view(st) >> (key_bits - span_bits)).view(w.dtype)
+
+
+def float_bits(seed: int, n: int, key_bits: int = 32) -> np.ndarray:
+    """Raw bits of IEEE 754 values: finite values of both signs over many
+    magnitudes, with one key in 16 drawn from the special values (signed
+    zeros, infinities, NaNs of both signs, smallest subnormals, extremes)."""
+    ft = np.float32 if key_bits == 32 else np.float64
+    u = unit_doubles(seed, 1, n)
+    e = (words(seed, 2, n) >> np.uint64(59)).astype(np.int64) - 16  # decades -16..15
+    x = ((u * 2.0 - 1.0) * 10.0 ** e).astype(ft)
+    out = x.view(np.uint32 if key_bits == 32 else np.uint64).copy()
+    if key_bits == 32:
+        specials = np.array([0x00000000, 0x80000000, 0x7F800000, 0xFF800000, 0x7FC00000,
+                             0xFFC00000, 0x00000001, 0x80000001, 0x7F7FFFFF, 0xFF7FFFFF,
+                             0x3F800000, 0xBF800000, 0x7F800001, 0xFF800123, 0x00800000,
+                             0x80800000], dtype=np.uint32)
+    else:
+        specials = np.array([0x0, 0x8000000000000000, 0x7FF0000000000000, 0xFFF0000000000000,
+                             0x7FF8000000000000, 0xFFF8000000000000, 0x1, 0x8000000000000001,
+                             0x7FEFFFFFFFFFFFFF, 0xFFEFFFFFFFFFFFFF, 0x3FF0000000000000,
+                             0xBFF0000000000000, 0x7FF0000000000001, 0xFFF0000000000123,
+                             0x0010000000000000, 0x8010000000000000], dtype=np.uint64)
+    pick = words(seed, 3, n)
+    special = (pick & np.uint64(15)) == np.uint64(0)
+    out[special] = specials[((pick[special] >> np.uint64(4)) & np.uint64(15)).astype(np.int64)]
+    return out
+
+
 DISTRIBUTIONS = ("and1", "and2", "and3", "and4", "zipf", "presorted", "reverse", "distinct16")
 
 
