@@ -74,7 +74,9 @@ constexpr int binning_waves_per_eu() {
 // segment its own chained scan and bin offsets); kBinDownsweep, the scatter
 // step of reduce-then-scan: every tile's exclusive prefix per digit is read
 // from a table that the upsweep and tile-scan kernels filled beforehand.
-template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode>
+// kOrdered: keys are ranked by their ordered bits (signed, floating-point or
+// descending order); false for unsigned ascending sorts.
+template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode, bool kOrdered>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(binning_waves_per_eu<K, kIpt>())))
     binning_kernel(BinningArgs<K> a) {
@@ -125,6 +127,10 @@ __global__ void __launch_bounds__(kBlock)
   const int width = a.width;
   const uint32_t mask = (1u << width) - 1u;
   const uint32_t n = a.n;
+  auto digit = [&](K k) -> uint32_t {
+    if constexpr (kOrdered) return digit_of(k, shift, mask, a.order);
+    else return digit_of(k, shift, mask);
+  };
 
   // The segmented grid is sized for the most tiles the offsets could need;
   // workgroups beyond the actual count leave before taking a tile id, so the
@@ -180,7 +186,8 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t idx = wave_base + i * kWave;
-      key[i] = idx < tile_end ? src[idx] : static_cast<K>(a.order.pad);
+      key[i] = idx < tile_end ? src[idx]
+                              : (kOrdered ? static_cast<K>(a.order.pad) : static_cast<K>(~K(0)));
     }
   }
 
@@ -200,7 +207,7 @@ __global__ void __launch_bounds__(kBlock)
         pos[r] += __shfl(prior[r], static_cast<int>(leader[r]), kWave);
       }
       if (i >= kIpt) continue;
-      const uint32_t d = digit_of(key[i], shift, mask, a.order);
+      const uint32_t d = digit(key[i]);
       uint32_t peers_lo = ~0u, peers_hi = ~0u;
 #pragma unroll
       for (int b = 0; b < kRadixBits; ++b) {
@@ -220,7 +227,7 @@ __global__ void __launch_bounds__(kBlock)
   } else {
 #pragma unroll
   for (int i = 0; i < kIpt; ++i) {
-    const uint32_t d = digit_of(key[i], shift, mask, a.order);
+    const uint32_t d = digit(key[i]);
     const uint32_t e = wave_table + d * kEntryWords;
     uint32_t peers_lo, peers_hi;
     if constexpr (kRank == kRankPresence) {
@@ -296,7 +303,7 @@ __global__ void __launch_bounds__(kBlock)
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kIpt; ++i)
-    pos[i] += s_rank[wave_table + digit_of(key[i], shift, mask, a.order) * kEntryWords];
+    pos[i] += s_rank[wave_table + digit(key[i]) * kEntryWords];
   __syncthreads();  // the rank tables are dead; the region now holds the tile
   const uint32_t uniform = kShortCircuit ? s_uniform : 0u;
 
@@ -392,7 +399,7 @@ __global__ void __launch_bounds__(kBlock)
     const uint32_t q = i * kBlock + tid;
     if (full || q < tile_count) {
       const K k = s_keys[q];
-      const uint32_t g = s_gbase[digit_of(k, shift, mask, a.order)] + q;
+      const uint32_t g = s_gbase[digit(k)] + q;
       if (!kCheckedStores || g < n) dst[g] = k;
       if constexpr (kVals) dst_idx[i] = g;
     }
@@ -553,11 +560,16 @@ BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
 
 hipError_t launch_binning(const BinningShape &s, int mode, const void *args, uint32_t grid,
                           hipStream_t stream) {
-#define ONESWEEP_LAUNCH(K, V, B, I, R, MODE)                                             \
-  if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) {                                                 \
-    hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, MODE>), dim3(grid), dim3(B), 0, stream, \
-                       *static_cast<const BinningArgs<K> *>(args));                       \
-    return hipGetLastError();                                                             \
+#define ONESWEEP_LAUNCH(K, V, B, I, R, MODE)                                              \
+  if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) {                                                  \
+    const BinningArgs<K> &a = *static_cast<const BinningArgs<K> *>(args);                  \
+    if (key_order_is_plain(a.order))                                                       \
+      hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, MODE, false>), dim3(grid), dim3(B), 0, \
+                         stream, a);                                                       \
+    else                                                                                   \
+      hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, MODE, true>), dim3(grid), dim3(B), 0, \
+                         stream, a);                                                       \
+    return hipGetLastError();                                                              \
   }
 #define ONESWEEP_LAUNCH_FLAT(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinChained)
 #define ONESWEEP_LAUNCH_SEG(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinSegmented)

@@ -129,6 +129,13 @@ __device__ __forceinline__ uint32_t count_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
+// Unsigned ascending order: the transform is the identity, and kernels are
+// instantiated without it (kOrdered = false) so that default sorts pay
+// nothing for it.
+__host__ __device__ inline bool key_order_is_plain(const KeyOrder &o) {
+  return (o.sign | o.negative | o.invert) == 0u;
+}
+
 template <typename K>
 __device__ __forceinline__ K ordered_bits(K key, const KeyOrder &o) {
   using S = typename std::make_signed<K>::type;

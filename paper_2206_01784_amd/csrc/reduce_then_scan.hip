@@ -25,7 +25,7 @@ namespace onesweep {
 // counter (copy = lane % kCopies, copy index fastest) keep lanes that share a
 // digit on different banks, bounding same-address serialisation of skewed
 // inputs to 64 / kCopies-way within one atomic instruction.
-template <typename K, int kBlock, int kIpt>
+template <typename K, int kBlock, int kIpt, bool kOrdered>
 __global__ void __launch_bounds__(kBlock) upsweep_kernel(UpsweepArgs<K> a) {
   constexpr int kCopies = 8;
   constexpr int kTile = kBlock * kIpt;
@@ -49,13 +49,17 @@ __global__ void __launch_bounds__(kBlock) upsweep_kernel(UpsweepArgs<K> a) {
   const int shift = a.shift;
   const uint32_t mask = (1u << a.width) - 1u;
   uint32_t *mine = s_count + (lane & (kCopies - 1));
+  auto digit = [&](K k) -> uint32_t {
+    if constexpr (kOrdered) return digit_of(k, shift, mask, a.order);
+    else return digit_of(k, shift, mask);
+  };
   K key[kIpt];
   if (count == static_cast<uint32_t>(kTile)) {
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) key[i] = src[wb + i * kWave];
 #pragma unroll
     for (int i = 0; i < kIpt; ++i)
-      __hip_atomic_fetch_add(&mine[digit_of(key[i], shift, mask, a.order) * kCopies], 1u,
+      __hip_atomic_fetch_add(&mine[digit(key[i]) * kCopies], 1u,
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   } else {
     const uint32_t end = base + count;
@@ -63,7 +67,7 @@ __global__ void __launch_bounds__(kBlock) upsweep_kernel(UpsweepArgs<K> a) {
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t idx = wb + i * kWave;
       if (idx < end)
-        __hip_atomic_fetch_add(&mine[digit_of(src[idx], shift, mask, a.order) * kCopies], 1u,
+        __hip_atomic_fetch_add(&mine[digit(src[idx]) * kCopies], 1u,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
@@ -143,8 +147,11 @@ hipError_t launch_upsweep(int key_bits, int block, int ipt, const void *args, ui
                           hipStream_t stream) {
 #define ONESWEEP_LAUNCH(K, B, I)                                                             \
   if (key_bits == 8 * (int)sizeof(K) && block == B && ipt == I) {                            \
-    hipLaunchKernelGGL((upsweep_kernel<K, B, I>), dim3(tiles), dim3(B), 0, stream,           \
-                       *static_cast<const UpsweepArgs<K> *>(args));                          \
+    const UpsweepArgs<K> &a = *static_cast<const UpsweepArgs<K> *>(args);                    \
+    if (key_order_is_plain(a.order))                                                         \
+      hipLaunchKernelGGL((upsweep_kernel<K, B, I, false>), dim3(tiles), dim3(B), 0, stream, a); \
+    else                                                                                     \
+      hipLaunchKernelGGL((upsweep_kernel<K, B, I, true>), dim3(tiles), dim3(B), 0, stream, a);  \
     return hipGetLastError();                                                                \
   }
   ONESWEEP_UPSWEEP_SHAPES(ONESWEEP_LAUNCH)

@@ -149,7 +149,7 @@ hipError_t launch_segment_clear(const SegmentClearArgs &a, uint32_t grid, hipStr
 // Digit counts of every place per large segment. Workgroups take tiles
 // cyclically, count into LDS (kCopies interleaved copies, as in the upfront
 // histogram) and add the non-zero counts to their segment's histograms.
-template <typename K>
+template <typename K, bool kOrdered>
 __global__ void __launch_bounds__(256) segment_histogram_kernel(SegmentHistArgs a) {
   constexpr int kMaxP = static_cast<int>(sizeof(K));
   constexpr int kCopies = 4;
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(256) segment_histogram_kernel(SegmentHistArgs 
 #pragma unroll
       for (int b = 0; b < kBatch; ++b) {
         if (base + b * 256 + tid >= info.y) continue;
-        const K o = ordered_bits(k[b], a.order);
+        const K o = kOrdered ? ordered_bits(k[b], a.order) : k[b];
 #pragma unroll
         for (int j = 0; j < kMaxP; ++j)
           if (j < places)
@@ -232,10 +232,22 @@ __global__ void __launch_bounds__(256) segment_scan_kernel(uint32_t *hist,
 
 hipError_t launch_segment_histogram(int key_bits, const SegmentHistArgs &a, uint32_t grid,
                                     hipStream_t stream) {
-  if (key_bits == 32)
-    hipLaunchKernelGGL(segment_histogram_kernel<uint32_t>, dim3(grid), dim3(256), 0, stream, a);
-  else
-    hipLaunchKernelGGL(segment_histogram_kernel<uint64_t>, dim3(grid), dim3(256), 0, stream, a);
+  const bool plain = key_order_is_plain(a.order);
+  if (key_bits == 32) {
+    if (plain)
+      hipLaunchKernelGGL((segment_histogram_kernel<uint32_t, false>), dim3(grid), dim3(256), 0,
+                         stream, a);
+    else
+      hipLaunchKernelGGL((segment_histogram_kernel<uint32_t, true>), dim3(grid), dim3(256), 0,
+                         stream, a);
+  } else {
+    if (plain)
+      hipLaunchKernelGGL((segment_histogram_kernel<uint64_t, false>), dim3(grid), dim3(256), 0,
+                         stream, a);
+    else
+      hipLaunchKernelGGL((segment_histogram_kernel<uint64_t, true>), dim3(grid), dim3(256), 0,
+                         stream, a);
+  }
   return hipGetLastError();
 }
 
@@ -299,7 +311,7 @@ constexpr int lds_sort_waves_per_eu() {
 #endif
 constexpr bool kLdsPresence = ONESWEEP_LDS_PRESENCE != 0;
 
-template <typename K, bool kVals, int kBlock, int kIpt>
+template <typename K, bool kVals, int kBlock, int kIpt, bool kOrdered>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(lds_sort_waves_per_eu<K, kBlock>())))
     lds_sort_kernel(LdsSortArgs a) {
@@ -346,7 +358,8 @@ __global__ void __launch_bounds__(kBlock)
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t q = wave_first + i * kWave + lane;
       // keys are held as their ordered bits from load to store
-      key[i] = q < len ? ordered_bits(kin[lo + q], a.order) : static_cast<K>(~static_cast<K>(0));
+      key[i] = q >= len ? static_cast<K>(~static_cast<K>(0))
+                        : (kOrdered ? ordered_bits(kin[lo + q], a.order) : kin[lo + q]);
       if constexpr (kVals) val[i] = q < len ? a.vals_in[lo + q] : 0u;
     }
     for (int j = 0; j < a.places; ++j) {
@@ -422,7 +435,7 @@ __global__ void __launch_bounds__(kBlock)
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t q = wave_first + i * kWave + lane;
       if (q < len) {
-        kout[lo + q] = original_bits(key[i], a.order);
+        kout[lo + q] = kOrdered ? original_bits(key[i], a.order) : key[i];
         if constexpr (kVals) a.vals_out[lo + q] = val[i];
       }
     }
@@ -439,15 +452,18 @@ int lds_class_block(int cls) { return kLdsBlock[cls]; }
 
 namespace {
 template <typename K, bool V, int B>
-const void *lds_kernel_ptr() {
-  return reinterpret_cast<const void *>(&lds_sort_kernel<K, V, B, kLdsIpt>);
+const void *lds_kernel_ptr(bool ordered) {
+  return ordered ? reinterpret_cast<const void *>(&lds_sort_kernel<K, V, B, kLdsIpt, true>)
+                 : reinterpret_cast<const void *>(&lds_sort_kernel<K, V, B, kLdsIpt, false>);
 }
 
-const void *lds_kernel(int key_bits, bool has_values, int cls) {
-#define ONESWEEP_LDS_PICK(B)                                                             \
-  if (key_bits == 32)                                                                    \
-    return has_values ? lds_kernel_ptr<uint32_t, true, B>() : lds_kernel_ptr<uint32_t, false, B>(); \
-  return has_values ? lds_kernel_ptr<uint64_t, true, B>() : lds_kernel_ptr<uint64_t, false, B>();
+const void *lds_kernel(int key_bits, bool has_values, int cls, bool ordered) {
+#define ONESWEEP_LDS_PICK(B)                                                                \
+  if (key_bits == 32)                                                                       \
+    return has_values ? lds_kernel_ptr<uint32_t, true, B>(ordered)                          \
+                      : lds_kernel_ptr<uint32_t, false, B>(ordered);                        \
+  return has_values ? lds_kernel_ptr<uint64_t, true, B>(ordered)                            \
+                    : lds_kernel_ptr<uint64_t, false, B>(ordered);
   switch (cls) {
     case 0: {
       ONESWEEP_LDS_PICK(64)
@@ -464,13 +480,14 @@ const void *lds_kernel(int key_bits, bool has_values, int cls) {
 }  // namespace
 
 hipError_t lds_sort_blocks_per_cu(int key_bits, bool has_values, int cls, int *blocks) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, lds_kernel(key_bits, has_values, cls),
-                                                      kLdsBlock[cls], 0);
+  // the ordered variants differ only at load and store
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks, lds_kernel(key_bits, has_values, cls, false), kLdsBlock[cls], 0);
 }
 
 hipError_t launch_lds_sort(int key_bits, bool has_values, const LdsSortArgs &a, uint32_t grid,
                            hipStream_t stream) {
-  const void *k = lds_kernel(key_bits, has_values, a.cls);
+  const void *k = lds_kernel(key_bits, has_values, a.cls, !key_order_is_plain(a.order));
   LdsSortArgs copy = a;
   void *params[] = {&copy};
   return hipLaunchKernel(k, dim3(grid), dim3(kLdsBlock[a.cls]), params, 0, stream);

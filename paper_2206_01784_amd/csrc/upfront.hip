@@ -18,7 +18,7 @@ namespace onesweep {
 // index fastest) keep lanes that share a digit on different LDS banks, which
 // bounds the serialisation of skewed inputs (all-equal keys) to
 // 64 / kCopies-way.
-template <typename K, int kBlock, int kVec, int kCopies>
+template <typename K, int kBlock, int kVec, int kCopies, bool kOrdered>
 __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
   constexpr int kMaxP = static_cast<int>(sizeof(K));  // 8-bit places in the key
   constexpr int kPerVec = 16 / static_cast<int>(sizeof(K));
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
   __syncthreads();
 
   auto count_key = [&](K k) {
-    const K t = ordered_bits(k, a.order);
+    const K t = kOrdered ? ordered_bits(k, a.order) : k;
 #pragma unroll
     for (int j = 0; j < kMaxP; ++j) {
       if (j < places) {
@@ -95,13 +95,21 @@ hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint
   if (key_bits == 32) {
     HistogramArgs<uint32_t> a{static_cast<const uint32_t *>(keys), hist, n, begin_bit, end_bit,
                               places, order};
-    hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies>),
-                       dim3(grid), dim3(kHistBlock), 0, stream, a);
+    if (key_order_is_plain(order))
+      hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies, false>),
+                         dim3(grid), dim3(kHistBlock), 0, stream, a);
+    else
+      hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies, true>),
+                         dim3(grid), dim3(kHistBlock), 0, stream, a);
   } else {
     HistogramArgs<uint64_t> a{static_cast<const uint64_t *>(keys), hist, n, begin_bit, end_bit,
                               places, order};
-    hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies>),
-                       dim3(grid), dim3(kHistBlock), 0, stream, a);
+    if (key_order_is_plain(order))
+      hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies, false>),
+                         dim3(grid), dim3(kHistBlock), 0, stream, a);
+    else
+      hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies, true>),
+                         dim3(grid), dim3(kHistBlock), 0, stream, a);
   }
   return hipGetLastError();
 }
