@@ -38,6 +38,8 @@ WORKLOADS = {
     "u32_keys_and8": (32, False, "and8", 28),
     "u32_keys_and16": (32, False, "and16", 28),
     "u64_keys_uniform": (64, False, "uniform", 27),
+    "f32_keys_mixed": (32, False, "float", 28),
+    "u32_keys_uniform_descending": (32, False, "uniform", 28),
     "u32_pairs_uniform": (32, True, "uniform", 28),
     "u64_pairs_uniform": (64, True, "uniform", 27),
     "u32_keys_uniform_2p20": (32, False, "uniform", 20),
@@ -152,8 +154,17 @@ def summarize_counters(fetch_csv, write_csv, workload="u32_keys_uniform"):
     print("\n".join(lines))
 
 
+# Key type and direction of the workloads that are not unsigned ascending.
+WORKLOAD_ORDER = {
+    "f32_keys_mixed": ("float", False),
+    "u32_keys_uniform_descending": ("unsigned", True),
+}
+
+
 def make_keys(dist, n, key_bits, seed=2):
     import workload as W
+    if dist == "float":
+        return W.float_bits(seed, n, key_bits)
     if dist == "uniform":
         return W.uniform(seed, n, key_bits)
     if dist == "equal":
@@ -466,8 +477,21 @@ def per_kind_summary(per_kind, ow, lengths, limits, pair_bytes=8):
     return {"table": table, "dominant": (kind, avg_us, launches), "roofline": roof}
 
 
+def is_sorted(out, key_kind, descending, np):
+    """Order check of a sorted output (floating-point keys: the finite values,
+    whose numeric order the sort must follow)."""
+    if key_kind == "float":
+        x = out.view(np.float32 if out.dtype == np.uint32 else np.float64)
+        out = x[np.isfinite(x)]
+    elif key_kind == "signed":
+        out = out.view(np.int32 if out.dtype == np.uint32 else np.int64)
+    if descending:
+        out = out[::-1]
+    return bool(np.all(out[1:] >= out[:-1]))
+
+
 def rts_baseline(ow, step, places, n, steps, stream, traced_configs, per_kind_times, onesweep_ms,
-                 d_kout, np):
+                 d_kout, np, key_kind="unsigned", descending=False):
     """The reduce-then-scan baseline (Section 2: upsweep, tile scan and
     downsweep per place, ~3pn memory operations against Onesweep's
     ~(2p+1)n) timed on the same input, tile shape and buffers, right after
@@ -484,8 +508,7 @@ def rts_baseline(ow, step, places, n, steps, stream, traced_configs, per_kind_ti
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / k
-    out = d_kout.cpu().numpy()
-    ok = bool(np.all(out[1:] >= out[:-1]))
+    ok = is_sorted(d_kout.cpu().numpy(), key_kind, descending, np)
     if not ok:
         log("[bench] ERROR: reduce-then-scan output is not sorted")
         sys.exit(1)
@@ -554,6 +577,9 @@ def main():
         run_segments(args)
         return
     key_bits, has_vals, dist, log2n = WORKLOADS[args.workload]
+    key_kind, descending = WORKLOAD_ORDER.get(args.workload, ("unsigned", False))
+    key_type = {"unsigned": ow.KEY_UNSIGNED, "signed": ow.KEY_SIGNED,
+                "float": ow.KEY_FLOAT}[key_kind]
     n = 1 << log2n
     log(f"[bench] workload={args.workload} n=2^{log2n} generating input")
     keys = make_keys(dist, n, key_bits)
@@ -583,7 +609,8 @@ def main():
             tr.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
             tr.capacity = launches
             cfgs.append(ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu,
-                                       rank_algorithm=args.rank, algorithm=alg, trace=tr))
+                                       rank_algorithm=args.rank, algorithm=alg,
+                                       key_type=key_type, descending=descending, trace=tr))
             holders.append((tr, evs, arr))
         return cfgs, holders
 
@@ -596,7 +623,8 @@ def main():
         return per_kind
 
     cfg_plain = ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu,
-                               rank_algorithm=args.rank, algorithm=algorithm)
+                               rank_algorithm=args.rank, algorithm=algorithm,
+                               key_type=key_type, descending=descending)
     cfgs, holders = traced_configs(algorithm, steps)
     temp_bytes = ow.sort_temp_bytes(n, key_bits, has_vals, config=cfg_plain)
     if not args.no_rts_baseline:
@@ -647,8 +675,7 @@ def main():
             f"avg={statistics.mean(ts) * 1e3:9.2f} us  total/step={sum(ts) / steps * 1e3:9.2f} us")
 
     # Correctness spot check of the timed result (full check lives in tests/).
-    out = d_kout.cpu().numpy()
-    sorted_ok = bool(np.all(out[1:] >= out[:-1]))
+    sorted_ok = is_sorted(d_kout.cpu().numpy(), key_kind, descending, np)
     if not sorted_ok:
         log("[bench] ERROR: output is not sorted")
         sys.exit(1)
@@ -681,10 +708,13 @@ def main():
         "dtype": "u32" if key_bits == 32 else "u64",
         "data": "synthetic",
         "config": {
-            "workload": f"stable sort of 2^{log2n} {dist} uint{key_bits} "
+            "workload": f"stable {'descending ' if descending else ''}sort of 2^{log2n} {dist} "
+                        f"{ {'unsigned': 'uint', 'signed': 'int', 'float': 'float'}[key_kind]}"
+                        f"{key_bits} "
                         f"{'(key, uint32 value) pairs' if has_vals else 'keys (keys only)'}, "
                         f"8-bit digits, {places} binning passes",
             "n": n, "key_bits": key_bits, "values": has_vals, "distribution": dist,
+            "key_type": key_kind, "descending": descending,
             "tile": ow.tile_items(key_bits, has_vals, cfg_plain, n),
             "hbm_fraction_whole_sort": round(whole_gbs / HBM_PEAK_GBS, 4),
         },
@@ -703,7 +733,7 @@ def main():
     if not args.no_rts_baseline and algorithm == ow.ALGORITHM_ONESWEEP:
         result["reduce_then_scan"] = rts_baseline(ow, step, places, n, steps, stream,
                                                   traced_configs, per_kind_times, ms_per_step,
-                                                  d_kout, np)
+                                                  d_kout, np, key_kind, descending)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(keys, vals)
