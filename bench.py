@@ -15,6 +15,7 @@ import ctypes
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -112,16 +113,18 @@ def summarize_counters(fetch_csv, write_csv, workload="u32_keys_uniform"):
     copy_bytes = n * (key_bits // 8 + (4 if has_vals else 0))
     fetch, write = _read_counters(fetch_csv), _read_counters(write_csv)
 
-    def pick(d, sub):
-        vals = [v for k, vs in d.items() if sub in k for v in vs]
+    def pick(d, pattern):
+        vals = [v for k, vs in d.items() if re.search(pattern, k) for v in vs]
         if not vals:
-            raise SystemExit(f"no dispatches of {sub} in the counter file")
+            raise SystemExit(f"no dispatches of {pattern} in the counter file")
         return vals
 
+    # the chained-scan binning kernel: template mode argument 0
+    binning = r"binning_kernel<[^<>]*, 0, (false|true)>"
     copy_f = max(pick(fetch, "copy_kernel")) * 1024
     copy_w = max(pick(write, "copy_kernel")) * 1024
-    bin_f = st.mean(pick(fetch, "binning_kernel")) * 1024
-    bin_w = st.mean(pick(write, "binning_kernel")) * 1024
+    bin_f = st.mean(pick(fetch, binning)) * 1024
+    bin_w = st.mean(pick(write, binning)) * 1024
     f_scale, w_scale = copy_bytes / copy_f, copy_bytes / copy_w
     traffic = bin_f * f_scale + bin_w * w_scale
     alg = n * 2 * (key_bits // 8 + (4 if has_vals else 0))
@@ -132,9 +135,11 @@ def summarize_counters(fetch_csv, write_csv, workload="u32_keys_uniform"):
         "# scale = bytes the plain copy kernel must move / its counter reading",
         "# commands (repo root; run from /tmp with TMPDIR=/tmp):",
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- "
-        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-cpu-baseline --calibrate-copy",
+        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-cpu-baseline "
+        "--no-rts-baseline --calibrate-copy",
         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o write -- "
-        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-cpu-baseline --calibrate-copy",
+        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-cpu-baseline "
+        "--no-rts-baseline --calibrate-copy",
         "#   python bench.py --workload " + workload + " --counters-summary <fetch csv> <write csv>",
         f"kernel_source_sha256_16: {kernel_source_hash()}",
         f"copy_fetch_kib: {copy_f / 1024:.1f}",
