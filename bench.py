@@ -44,6 +44,7 @@ WORKLOADS = {
     "u32_pairs_uniform": (32, True, "uniform", 28),
     "u64_pairs_uniform": (64, True, "uniform", 27),
     "u32_keys_uniform_2p20": (32, False, "uniform", 20),
+    "u32_keys_uniform_2p30": (32, False, "uniform", 30),
 }
 # Batched segmented workload: S segments with log-normal lengths (median 2000,
 # sigma 1.5, cap 2^22) scaled to 2^26 keys in total; uniform uint32 keys,
@@ -67,9 +68,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(launch_bytes_alg: float):
+def read_traffic(workload: str):
     """HBM traffic per binning launch from the committed rocprofv3 counter
-    summary, or None when it is missing or the kernel source changed since."""
+    summary, or None when it is missing, covers another workload, or the
+    kernel source changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -79,6 +81,8 @@ def read_traffic(launch_bytes_alg: float):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if kv.get("workload") != workload:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -142,6 +146,7 @@ def summarize_counters(fetch_csv, write_csv, workload="u32_keys_uniform"):
         "--no-rts-baseline --calibrate-copy",
         "#   python bench.py --workload " + workload + " --counters-summary <fetch csv> <write csv>",
         f"kernel_source_sha256_16: {kernel_source_hash()}",
+        f"workload: {workload}",
         f"copy_fetch_kib: {copy_f / 1024:.1f}",
         f"copy_write_kib: {copy_w / 1024:.1f}",
         f"copy_true_bytes_each_way: {copy_bytes}",
@@ -600,10 +605,18 @@ def main():
     algorithm = (ow.ALGORITHM_REDUCE_THEN_SCAN if args.algorithm == "reduce-then-scan"
                  else ow.ALGORITHM_ONESWEEP)
 
+    # Onesweep bins inputs above 2^28 keys in strips: one launch per strip
+    # and place (each strip at most 2^28 keys, whole tiles).
+    tile = ow.tile_items(key_bits, has_vals, ow.make_config(args.block, args.ipt,
+                                                           rank_algorithm=args.rank), n)
+    tiles = -(-n // tile)
+    strips = -(-tiles // max(1, (1 << 28) // tile))
+
     def traced_configs(alg, count):
         """`count` configs, each recording HIP events around every launch on
         the stream the kernels run on."""
-        launches = 3 + places * (3 if alg == ow.ALGORITHM_REDUCE_THEN_SCAN else 1) + 1
+        rts_alg = alg == ow.ALGORITHM_REDUCE_THEN_SCAN
+        launches = min(ow.TRACE_MAX, 3 + places * (3 if rts_alg else strips) + 1)
         cfgs, holders = [], []
         for _ in range(count):
             evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * launches)]
@@ -691,10 +704,13 @@ def main():
                     else ow.KERNEL_BINNING)
     bin_ts = per_kind.get(scatter_kind, [])
     binning_avg_s = statistics.mean(bin_ts) * 1e-3 if bin_ts else float("nan")
-    launch_bytes = n * 2 * (kb + vb)  # each binning pass reads and writes every element once
+    # each binning pass reads and writes every element once, over `strips`
+    # launches (the reduce-then-scan downsweep: one launch)
+    pass_bytes = n * 2 * (kb + vb)
+    launch_bytes = pass_bytes // (strips if algorithm == ow.ALGORITHM_ONESWEEP else 1)
     achieved = launch_bytes / binning_avg_s / 1e9
-    traffic = read_traffic(launch_bytes) if algorithm == ow.ALGORITHM_ONESWEEP else None
-    sort_bytes = n * kb + places * launch_bytes  # (2p+1)n element moves
+    traffic = read_traffic(args.workload) if algorithm == ow.ALGORITHM_ONESWEEP else None
+    sort_bytes = n * kb + places * pass_bytes  # (2p+1)n element moves
     whole_gbs = sort_bytes / (ms_per_step * 1e-3) / 1e9
     log(f"[bench] whole sort: {whole_gbs:.1f} GB/s algorithmic = {whole_gbs / HBM_PEAK_GBS:.3f} "
         f"of peak; binning: {achieved:.1f} GB/s")

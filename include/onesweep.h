@@ -21,8 +21,10 @@
  *    asynchronous; results are valid after the caller synchronises. The
  *    enqueued sequence uses kernels only (no memset or memcpy nodes), so a
  *    caller may capture it into a HIP graph.
- *  - Keys are unsigned 32- or 64-bit integers ordered ascending by the bit
- *    field [begin_bit, end_bit) (0 <= begin_bit <= end_bit <= key_bits); the
+ *  - Keys are 32- or 64-bit words ordered by the bit field
+ *    [begin_bit, end_bit) (0 <= begin_bit <= end_bit <= key_bits) of their
+ *    ordered bits: unsigned integers by default, signed or IEEE 754 keys and
+ *    descending order through onesweep_config_t.key_type / descending; the
  *    whole key word is carried to the output. Values are opaque 32-bit
  *    payloads that travel with their keys.
  *  - Digit places are 8 bits wide (r = 256 bins); place j covers bits
@@ -31,9 +33,11 @@
  *  - The output is always stable, because an LSD sort is stable by
  *    construction (Section 1); the `stable` argument is accepted for
  *    interface symmetry and ignored.
- *  - n must be below 2^30: the chained-scan status words hold 30-bit values
- *    (Section 3, "Handling very large problems"). Larger n returns
- *    ONESWEEP_ERROR_TOO_LARGE.
+ *  - The chained-scan status words hold 30-bit values (Section 3, "Handling
+ *    very large problems"): one chained scan covers fewer than 2^30 keys.
+ *    Whole plain sorts (onesweep_sort_keys/pairs) bin large inputs in strips
+ *    of at most 2^28 keys and accept n below 2^31; the other entry points
+ *    accept n below 2^30. Larger n returns ONESWEEP_ERROR_TOO_LARGE.
  *  - Errors are returned as status codes; nothing is enqueued when argument
  *    validation fails. onesweep_last_error() describes the last failure of
  *    the calling thread.
@@ -53,7 +57,7 @@ typedef struct ihipStream_t *onesweep_stream_t; /* same type as hipStream_t */
 typedef enum {
     ONESWEEP_SUCCESS = 0,
     ONESWEEP_ERROR_INVALID_VALUE = 1,     /* bad pointer, width, bit range, overlap */
-    ONESWEEP_ERROR_TOO_LARGE = 2,         /* n >= 2^30 */
+    ONESWEEP_ERROR_TOO_LARGE = 2,         /* n beyond the entry point's limit (2^31 or 2^30) */
     ONESWEEP_ERROR_INSUFFICIENT_TEMP = 3, /* *temp_bytes below the required size */
     ONESWEEP_ERROR_HIP = 4,               /* a HIP runtime call failed */
     ONESWEEP_ERROR_UNSUPPORTED = 5        /* configuration not built into the library */
@@ -153,6 +157,13 @@ typedef struct {
     int descending;          /* 1: descending order (digits of the complemented
                                 transformed key), still stable: equal keys keep their
                                 input order. 0: ascending. */
+    int strip_log2;          /* onesweep_sort_keys/pairs only: each binning pass runs
+                                as consecutive strips of at most 2^strip_log2 keys
+                                (whole tiles, at least one), each strip its own
+                                chained scan whose last tile hands the next strip its
+                                bin starts (Section 3, handling very large problems).
+                                0 = 28, the default; else 11..28. Smaller strips only
+                                serve tests of inputs below 2^28. */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 

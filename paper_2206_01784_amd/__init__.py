@@ -50,7 +50,7 @@ class Config(ctypes.Structure):
                 ("rank_algorithm", ctypes.c_int), ("segment_limits", ctypes.c_int * 3),
                 ("segment_streams", ctypes.c_int), ("algorithm", ctypes.c_int),
                 ("key_type", ctypes.c_int), ("descending", ctypes.c_int),
-                ("trace", ctypes.POINTER(Trace))]
+                ("strip_log2", ctypes.c_int), ("trace", ctypes.POINTER(Trace))]
 
 
 _vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
@@ -105,10 +105,11 @@ KEY_UNSIGNED, KEY_SIGNED, KEY_FLOAT = 0, 1, 2
 def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,
                 digit_bits: int = 0, rank_algorithm: int = 0, segment_limits=(0, 0, 0),
                 segment_streams: int = 0, algorithm: int = 0, key_type: int = 0,
-                descending: bool = False, trace: Trace | None = None) -> Config:
+                descending: bool = False, strip_log2: int = 0,
+                trace: Trace | None = None) -> Config:
     c = Config(digit_bits, block_threads, items_per_thread, hist_blocks_per_cu, rank_algorithm,
                (ctypes.c_int * 3)(*segment_limits), segment_streams, algorithm, key_type,
-               int(descending), None)
+               int(descending), strip_log2, None)
     if trace is not None:
         c.trace = ctypes.pointer(trace)
     return c

@@ -34,7 +34,12 @@ void clear_error() { g_error[0] = '\0'; }
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kMaxN = size_t(1) << 30;  // 30-bit status values
+constexpr size_t kMaxN = size_t(1) << 30;  // 30-bit status values, one chained scan
+// Whole plain sorts run large inputs as strips of at most 2^28 keys per
+// binning pass (each strip its own chained scan), so 30-bit status values
+// never overflow; 32-bit element indices keep a factor-2 headroom below 2^31.
+constexpr size_t kMaxSortN = size_t(1) << 31;
+constexpr int kDefaultStripLog2 = 28;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -69,6 +74,7 @@ onesweep_status_t device_cus(int *cus) {
 struct Resolved {
   BinningShape shape;
   int hist_blocks_per_cu;
+  int strip_log2;
   int algorithm;  // onesweep_algorithm_t
   KeyOrder order;
   onesweep_trace_t *trace;
@@ -100,6 +106,7 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
   r->shape = binning_default_shape(key_bits, has_values, n);
   r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
   r->algorithm = ONESWEEP_ALGORITHM_ONESWEEP;
+  r->strip_log2 = kDefaultStripLog2;
   r->order = key_order(key_bits, ONESWEEP_KEY_UNSIGNED, false);
   r->trace = nullptr;
   if (cfg != nullptr) {
@@ -123,6 +130,10 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
                   "algorithm %d: reduce-then-scan is offered by whole plain sorts only",
                   cfg->algorithm);
     r->algorithm = cfg->algorithm;
+    if (cfg->strip_log2 != 0 && (cfg->strip_log2 < 11 || cfg->strip_log2 > kDefaultStripLog2))
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "strip_log2 %d not 0 or in [11, %d]",
+                  cfg->strip_log2, kDefaultStripLog2);
+    if (cfg->strip_log2 != 0) r->strip_log2 = cfg->strip_log2;
     if (cfg->key_type < ONESWEEP_KEY_UNSIGNED || cfg->key_type > ONESWEEP_KEY_FLOAT)
       return fail(ONESWEEP_ERROR_INVALID_VALUE, "key_type %d not 0, 1 or 2", cfg->key_type);
     if (cfg->descending != 0 && cfg->descending != 1)
@@ -149,24 +160,32 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
 // counters, status words) is contiguous so one kernel clears it.
 struct SortLayout {
   size_t hist, counters, status, zero_end;
-  size_t offsets, plan, tmp_keys, tmp_vals, total;
+  size_t offsets, strip_offsets, plan, tmp_keys, tmp_vals, total;
   uint32_t tiles;
+  uint32_t strip_tiles, strips;  // tiles per strip, strips per binning pass
   size_t status_words_per_place;
 };
 
 // Reduce-then-scan keeps one count table of the same size as a place's
 // status words, reused by every place and not cleared (the upsweep writes
 // every entry); only the histograms and tile counters are cleared.
+// Onesweep strips: `strip_log2` bounds a strip to 2^strip_log2 keys (whole
+// tiles, at least one); strip k > 0 of place j reads its bin starts from
+// strip_offsets[(j * strips + k) * 256], written by strip k - 1. Each
+// (place, strip) has its own tile counter.
 SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size_t tile,
-                       bool rts = false) {
+                       bool rts = false, int strip_log2 = kDefaultStripLog2) {
   SortLayout L{};
   L.tiles = static_cast<uint32_t>((n + tile - 1) / tile);
   L.status_words_per_place = static_cast<size_t>(L.tiles) * kRadix;
+  L.strip_tiles = static_cast<uint32_t>(std::max<size_t>(1, (size_t(1) << strip_log2) / tile));
+  L.strips = rts ? 1u : std::max<uint32_t>(1u, (L.tiles + L.strip_tiles - 1) / L.strip_tiles);
+  if (rts) L.strip_tiles = std::max<uint32_t>(L.tiles, 1u);
   size_t off = 0;
   L.hist = off;
   off += align_up(sizeof(uint32_t) * kMaxPlaces * kRadix);
   L.counters = off;
-  off += kAlign;
+  off += align_up(sizeof(uint32_t) * static_cast<size_t>(std::max(places, 1)) * L.strips);
   L.status = off;
   if (rts) {
     L.zero_end = off;
@@ -177,6 +196,9 @@ SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size
   }
   L.offsets = off;
   off += align_up(sizeof(uint32_t) * kMaxPlaces * kRadix);
+  L.strip_offsets = off;
+  if (L.strips > 1)
+    off += align_up(sizeof(uint32_t) * kRadix * static_cast<size_t>(places) * L.strips);
   L.plan = off;
   off += kAlign;
   L.tmp_keys = off;
@@ -223,15 +245,16 @@ struct Tracer {
   } while (0)
 
 onesweep_status_t check_common(size_t *temp_bytes, size_t n, int key_bits, int begin_bit,
-                               int end_bit) {
+                               int end_bit, size_t max_n = kMaxN) {
   if (temp_bytes == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp_bytes is NULL");
   if (key_bits != 32 && key_bits != 64)
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "key_bits %d is not 32 or 64", key_bits);
   if (begin_bit < 0 || begin_bit > end_bit || end_bit > key_bits)
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "bit range [%d, %d) invalid for %d-bit keys",
                 begin_bit, end_bit, key_bits);
-  if (n >= kMaxN)
-    return fail(ONESWEEP_ERROR_TOO_LARGE, "n = %zu is not below 2^30", n);
+  if (n >= max_n)
+    return fail(ONESWEEP_ERROR_TOO_LARGE, "n = %zu is not below 2^%d", n,
+                max_n == kMaxSortN ? 31 : 30);
   return ONESWEEP_SUCCESS;
 }
 
@@ -240,14 +263,14 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
                             bool has_values, size_t n, int key_bits, int begin_bit, int end_bit,
                             const onesweep_config_t *cfg, hipStream_t stream) {
   g_error[0] = '\0';
-  onesweep_status_t st = check_common(temp_bytes, n, key_bits, begin_bit, end_bit);
+  onesweep_status_t st = check_common(temp_bytes, n, key_bits, begin_bit, end_bit, kMaxSortN);
   if (st) return st;
   Resolved rc;
   if ((st = resolve(key_bits, has_values, n, cfg, &rc, kCallSort))) return st;
   const int places = num_places(begin_bit, end_bit);
   const size_t tile = binning_tile_items(rc.shape);
   const bool rts = rc.algorithm == ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN;
-  const SortLayout L = sort_layout(n, key_bits, has_values, places, tile, rts);
+  const SortLayout L = sort_layout(n, key_bits, has_values, places, tile, rts, rc.strip_log2);
   if (d_temp == nullptr) {
     *temp_bytes = L.total;
     return ONESWEEP_SUCCESS;
@@ -326,73 +349,58 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_SCAN, "scan",
                   launch_scan(hist, offsets, plan, places, static_cast<uint32_t>(n), alias,
                               stream));
-  for (int j = 0; j < places; ++j) {
+  uint32_t *strip_offsets = reinterpret_cast<uint32_t *>(temp + L.strip_offsets);
+  // One place: the reduce-then-scan upsweep and tile scan when that algorithm
+  // runs, then the binning (or downsweep) launches, one per strip.
+  auto bin_place = [&](auto key_tag, int j) -> onesweep_status_t {
+    using K = decltype(key_tag);
     const int lo = begin_bit + j * kRadixBits;
     const int width = (lo + kRadixBits <= end_bit) ? kRadixBits : end_bit - lo;
     // Onesweep: place j's own status words; reduce-then-scan: the shared
     // count table, filled by the upsweep and scanned before the downsweep.
     uint32_t *table = rts ? status : status + j * L.status_words_per_place;
-    const int mode = rts ? kBinDownsweep : kBinChained;
-    const int kind = rts ? ONESWEEP_KERNEL_DOWNSWEEP : ONESWEEP_KERNEL_BINNING;
-    if (key_bits == 32) {
-      if (rts) {
-        UpsweepArgs<uint32_t> u{};
-        for (int b = 0; b < 3; ++b) u.keys[b] = static_cast<uint32_t *>(ca.keys[b]);
-        u.plan = plan;
-        u.order = rc.order;
-        u.counts = table;
-        u.n = static_cast<uint32_t>(n);
-        u.place = j;
-        u.shift = lo;
-        u.width = width;
-        ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_UPSWEEP, "upsweep",
-                        launch_upsweep(32, rc.shape.block, rc.shape.ipt, &u, L.tiles, stream));
-        ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_TILE_SCAN, "tile scan",
-                        launch_tile_scan(table, L.tiles, plan, j, stream));
-      }
-      BinningArgs<uint32_t> a{};
-      for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<uint32_t *>(ca.keys[b]);
-      for (int b = 0; b < 3; ++b) a.vals[b] = ca.vals[b];
-      a.bin_offsets = offsets + j * kRadix;
-      a.status = table;
-      a.tile_counter = counters + j;
-      a.plan = plan;
-      a.order = rc.order;
-      a.n = static_cast<uint32_t>(n);
-      a.place = j;
-      a.shift = lo;
-      a.width = width;
-      ONESWEEP_LAUNCH(tr, kind, "binning", launch_binning(rc.shape, mode, &a, L.tiles, stream));
-    } else {
-      if (rts) {
-        UpsweepArgs<uint64_t> u{};
-        for (int b = 0; b < 3; ++b) u.keys[b] = static_cast<uint64_t *>(ca.keys[b]);
-        u.plan = plan;
-        u.order = rc.order;
-        u.counts = table;
-        u.n = static_cast<uint32_t>(n);
-        u.place = j;
-        u.shift = lo;
-        u.width = width;
-        ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_UPSWEEP, "upsweep",
-                        launch_upsweep(64, rc.shape.block, rc.shape.ipt, &u, L.tiles, stream));
-        ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_TILE_SCAN, "tile scan",
-                        launch_tile_scan(table, L.tiles, plan, j, stream));
-      }
-      BinningArgs<uint64_t> a{};
-      for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<uint64_t *>(ca.keys[b]);
-      for (int b = 0; b < 3; ++b) a.vals[b] = ca.vals[b];
-      a.bin_offsets = offsets + j * kRadix;
-      a.status = table;
-      a.tile_counter = counters + j;
-      a.plan = plan;
-      a.order = rc.order;
-      a.n = static_cast<uint32_t>(n);
-      a.place = j;
-      a.shift = lo;
-      a.width = width;
-      ONESWEEP_LAUNCH(tr, kind, "binning", launch_binning(rc.shape, mode, &a, L.tiles, stream));
+    if (rts) {
+      UpsweepArgs<K> u{};
+      for (int b = 0; b < 3; ++b) u.keys[b] = static_cast<K *>(ca.keys[b]);
+      u.plan = plan;
+      u.order = rc.order;
+      u.counts = table;
+      u.n = static_cast<uint32_t>(n);
+      u.place = j;
+      u.shift = lo;
+      u.width = width;
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_UPSWEEP, "upsweep",
+                      launch_upsweep(key_bits, rc.shape.block, rc.shape.ipt, &u, L.tiles,
+                                     stream));
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_TILE_SCAN, "tile scan",
+                      launch_tile_scan(table, L.tiles, plan, j, stream));
     }
+    uint32_t *place_strips = strip_offsets + static_cast<size_t>(j) * L.strips * kRadix;
+    for (uint32_t k = 0; k < L.strips; ++k) {
+      BinningArgs<K> a{};
+      for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<K *>(ca.keys[b]);
+      for (int b = 0; b < 3; ++b) a.vals[b] = ca.vals[b];
+      a.bin_offsets = k == 0 ? offsets + j * kRadix : place_strips + k * kRadix;
+      a.next_bin_offsets = k + 1 < L.strips ? place_strips + (k + 1) * kRadix : nullptr;
+      a.tile_first = k * L.strip_tiles;
+      a.status = table;
+      a.tile_counter = counters + static_cast<size_t>(j) * L.strips + k;
+      a.plan = plan;
+      a.order = rc.order;
+      a.n = static_cast<uint32_t>(n);
+      a.place = j;
+      a.shift = lo;
+      a.width = width;
+      const uint32_t grid = std::min(L.strip_tiles, L.tiles - a.tile_first);
+      ONESWEEP_LAUNCH(tr, rts ? ONESWEEP_KERNEL_DOWNSWEEP : ONESWEEP_KERNEL_BINNING, "binning",
+                      launch_binning(rc.shape, rts ? kBinDownsweep : kBinChained, &a, grid,
+                                     stream));
+    }
+    return ONESWEEP_SUCCESS;
+  };
+  for (int j = 0; j < places; ++j) {
+    st = key_bits == 32 ? bin_place(uint32_t{}, j) : bin_place(uint64_t{}, j);
+    if (st) return st;
   }
   ca.plan = plan;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_COPY, "copy", launch_copy(ca, stream_grid, stream));

@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(kBlock)
     s_uniform = 0u;
   }
   __syncthreads();
-  const uint32_t tile = s_tile;
+  const uint32_t tile = s_tile + a.tile_first;  // tickets count from the strip's start
   uint32_t tile_base, tile_count, bin_base;
   const uint32_t *bin_offsets;
   bool first;
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(kBlock)
     tile_base = tile * static_cast<uint32_t>(kTile);
     tile_count = min(n - tile_base, static_cast<uint32_t>(kTile));
     bin_base = 0u;
-    first = tile == 0u;
+    first = tile == a.tile_first;
     bin_offsets = a.bin_offsets;
   }
   const uint32_t tile_end = tile_base + tile_count;
@@ -337,11 +337,12 @@ __global__ void __launch_bounds__(kBlock)
       exclusive = a.status[static_cast<size_t>(tid) * tiles + tile];
     } else if (!first) {
       int pred = static_cast<int>(tile) - 1;
+      const int chain_first = static_cast<int>(a.tile_first);  // 0 in a segmented sort
       while (true) {
         uint32_t s[kLookback];
 #pragma unroll
         for (int w = 0; w < kLookback; ++w)
-          s[w] = pred - w >= 0
+          s[w] = pred - w >= chain_first
                      ? load_status(&a.status[static_cast<size_t>(pred - w) * kRadix + tid])
                      : kFlagG;
         bool found = false, stalled = false;
@@ -369,6 +370,10 @@ __global__ void __launch_bounds__(kBlock)
     // Global position of the key at tile position q with digit v is
     // s_gbase[v] + q (unsigned wrap-around cancels in the sum).
     s_gbase[tid] = bin_start + exclusive - local_start;
+    // The strip's last tile hands the next strip its bin starts.
+    if constexpr (kMode == kBinChained)
+      if (a.next_bin_offsets != nullptr && tile + 1u == a.tile_first + gridDim.x)
+        a.next_bin_offsets[tid] = bin_start + exclusive + published;
   }
   __syncthreads();
 

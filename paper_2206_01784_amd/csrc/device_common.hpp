@@ -90,6 +90,12 @@ struct BinningArgs {
   const PassPlan *plan;        // NULL: run unconditionally in -> out
   SegmentTiles seg;            // segmented sort only
   KeyOrder order;
+  // Strips of a large sort (Section 3, handling very large problems): this
+  // launch bins the tiles [tile_first, tile_first + grid) as one chained
+  // scan, and its last tile writes bin_offsets + the strip's digit counts to
+  // next_bin_offsets, the bin starts of the next strip (NULL: last strip).
+  uint32_t tile_first;
+  uint32_t *next_bin_offsets;
   uint32_t n;
   int place;
   int shift;

@@ -53,7 +53,7 @@ def test_temp_size_query_needs_no_gpu():
     (dict(key_bits=48), 1),
     (dict(begin_bit=9, end_bit=8), 1),
     (dict(end_bit=33), 1),
-    (dict(n=1 << 30), 2),
+    (dict(n=1 << 31), 2),
 ])
 def test_invalid_arguments_are_rejected_on_the_host(kwargs, code):
     import paper_2206_01784_amd as ow
@@ -141,6 +141,35 @@ def test_key_type_and_direction_validation_needs_no_gpu():
             cfg = ow.make_config(key_type=kt, descending=desc)
             assert ow.sort_temp_bytes(1000, 64, True, config=cfg) == \
                 ow.sort_temp_bytes(1000, 64, True)
+
+
+def test_strip_configuration_and_size_limits_need_no_gpu():
+    """Whole plain sorts accept n up to 2^31 - 1 (strips of at most 2^28
+    keys per chained scan); the single-pass, histogram and segmented entry
+    points keep one chained scan and the 2^30 limit."""
+    import paper_2206_01784_amd as ow
+    lib = ow.library()
+    size = ctypes.c_size_t(0)
+    n = (1 << 31) - 1
+    big = ow.sort_temp_bytes(n, 32)
+    assert big >= 4 * n
+    assert ow.sort_temp_bytes(n, 32, True) >= 8 * n
+    # strip bin starts: one 256-word row per (place, strip) after the first
+    one = ow.sort_temp_bytes(1 << 20, 32)
+    strips = ow.sort_temp_bytes(1 << 20, 32, config=ow.make_config(strip_log2=14))
+    assert strips - one >= (64 - 1) * 256 * 4
+    for bad in (10, 29, -1):
+        cfg = ow.make_config(strip_log2=bad)
+        rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
+                                    ctypes.byref(cfg), None)
+        assert rc == ow.ERROR_INVALID_VALUE, bad
+    assert lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 1 << 31, 32, 0, 32, 1,
+                                  None, None) == ow.ERROR_TOO_LARGE
+    assert lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, None, None, 1 << 30,
+                                      None, 1, 32, 0, 32, 1, None,
+                                      None) == ow.ERROR_TOO_LARGE
+    assert lib.onesweep_binning_pass(None, ctypes.byref(size), None, None, None, None, 1 << 30,
+                                     32, 0, 8, None, None, None) == ow.ERROR_TOO_LARGE
 
 
 def test_insufficient_temp_and_null_pointers():

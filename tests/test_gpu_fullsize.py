@@ -111,3 +111,19 @@ def test_full_segments_lognormal_20000(ow):
     wk, wv = oracle.sort_segments(keys, off, vals)
     assert np.array_equal(ko.cpu().numpy(), wk)
     assert np.array_equal(vo.cpu().numpy(), wv)
+
+
+def test_full_keys_beyond_2p30(ow):
+    """2^30 + 4097 uint32 keys: five strips of 2^28 keys per binning pass;
+    bit-exact against the oracle at full size."""
+    n = (1 << 30) + 4097
+    print(f"[full] 2^30 + 4097 u32 keys, n={n}", flush=True)
+    keys = W.uniform(91, n)
+    d = torch.from_numpy(keys).cuda()
+    out = ow.sort_keys(d)
+    del d
+    got = out.cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    want = oracle.sort(keys)[0]
+    assert np.array_equal(got, want)

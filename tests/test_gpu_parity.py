@@ -374,3 +374,55 @@ def test_reduce_then_scan_trace_and_graph_replay(ow):
         eager = ow.sort_keys(dev(k[: n // 3]), config=cfg)
         torch.cuda.synchronize()
         assert np.array_equal(host(eager), oracle.sort(k[: n // 3])[0])
+
+
+# ------------------------------------------------------------------ strips (large inputs)
+
+@pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
+def test_sorts_in_strips(ow, kb, vals):
+    """Binning passes split into strips, each its own chained scan seeded by
+    the previous strip's bin starts (Section 3, very large problems): forced
+    here with small strips, including one-tile strips and a ragged last strip,
+    every shape, typed and descending keys, and partial bit ranges."""
+    for block, ipt in SHAPES[(kb, vals)]:
+        T = block * ipt
+        for strip_log2 in (11, 15):
+            cfg = ow.make_config(block, ipt, strip_log2=strip_log2)
+            n = 9 * T + 1234
+            keys = W.uniform(61 + strip_log2, n, kb)
+            v = np.arange(n, dtype=np.uint32) if vals else None
+            check_sort(ow, keys, v, 0, kb, cfg)
+    cfg = ow.make_config(strip_log2=14)
+    n = 100003
+    v = np.arange(n, dtype=np.uint32) if vals else None
+    keys = W.and_of_q(63, 2, n, kb)
+    check_sort(ow, keys, v, 3, kb - 2, cfg)
+    check_sort(ow, keys, v, 0, kb, cfg, inplace=True)
+    signed = W.signed_ints(64, n, kb)
+    got = ow.sort_keys(dev(signed.view(np.int32 if kb == 32 else np.int64)), config=cfg,
+                       descending=True)
+    want = oracle.sort(signed, None, key_type=oracle.KEY_SIGNED, descending=True)[0]
+    assert np.array_equal(host(got).view(signed.dtype), want)
+
+
+def test_strip_trace_launch_sequence(ow):
+    import ctypes
+    n = 200001
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * 64)]
+    for e in events:
+        e.record()
+    torch.cuda.synchronize()
+    arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+    tr = ow.Trace()
+    tr.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    tr.capacity = 64
+    cfg = ow.make_config(1024, 8, strip_log2=16, trace=tr)  # 8 tiles per strip, 4 strips
+    keys = W.uniform(65, n)
+    out = ow.sort_keys(dev(keys), config=cfg)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(out), oracle.sort(keys)[0])
+    kinds = [tr.kinds[i] for i in range(tr.count)]
+    strips = -(-(-(-n // 8192)) // 8)
+    assert strips == 4
+    assert kinds == [ow.KERNEL_RESET, ow.KERNEL_HISTOGRAM, ow.KERNEL_SCAN] + \
+        [ow.KERNEL_BINNING] * (4 * strips) + [ow.KERNEL_COPY]
