@@ -272,7 +272,10 @@ onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
  * (the input is sorted many times). Temp storage: the largest any candidate
  * needs (size query with d_temp == NULL). Unlike the sort, this call creates
  * two HIP events and synchronises on them; it is not graph-capturable.
- * cfg_out->trace is NULL on return; cfg_out may be NULL for the size query.
+ * On input, cfg_out->key_type and cfg_out->descending select the key order
+ * (other fields are ignored); on return *cfg_out is the chosen configuration
+ * with that order and a NULL trace. cfg_out may be NULL for the size query
+ * (unsigned ascending).
  */
 onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
                                          const void *d_keys_in, void *d_keys_out,

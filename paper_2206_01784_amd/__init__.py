@@ -354,9 +354,10 @@ def sort_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tenso
 def tune_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tensor | None = None,
                   begin_bit: int = 0, end_bit: int | None = None,
                   keys_out: torch.Tensor | None = None, values_out: torch.Tensor | None = None,
-                  repetitions: int = 3, stream=None) -> Config:
+                  repetitions: int = 3, stream=None, descending: bool = False) -> Config:
     """Time the segmented sort's candidate configurations on this data and
-    return the fastest (the outputs hold the sorted segments afterwards)."""
+    return the fastest (the outputs hold the sorted segments afterwards).
+    Key types as in sort_keys; the returned config keeps the key order."""
     kb = _key_bits(keys)
     end_bit = kb if end_bit is None else end_bit
     n = keys.numel()
@@ -369,7 +370,7 @@ def tune_segments(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tenso
     _check(_lib.onesweep_tune_segments(None, ctypes.byref(size), None, None, dummy, dummy, n, None,
                                        num_segments, kb, begin_bit, end_bit, repetitions, None,
                                        None))
-    cfg = Config()
+    cfg = _ordered_config(None, keys, descending) or Config()
     temp = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=keys.device)
     size = ctypes.c_size_t(temp.numel())
     _check(_lib.onesweep_tune_segments(_dev_ptr(temp), ctypes.byref(size), _dev_ptr(keys),

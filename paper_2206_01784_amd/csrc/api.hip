@@ -969,8 +969,13 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
   static const int kLimits[][3] = {{0, 0, 0},   {0, 0, 4096},  {0, 0, 2048}, {0, 0, -1},
                                    {0, -1, 0},  {-1, 0, 0},    {256, 1024, 4096}};
   constexpr int kNumShapes = 3, kNumLimits = sizeof(kLimits) / sizeof(kLimits[0]);
+  // The key order comes in through *cfg_out and is kept by every candidate.
+  const int key_type = cfg_out ? cfg_out->key_type : ONESWEEP_KEY_UNSIGNED;
+  const int descending = cfg_out ? cfg_out->descending : 0;
   auto candidate = [&](int i) {
     onesweep_config_t c{};
+    c.key_type = key_type;
+    c.descending = descending;
     const int(*shapes)[2] = key_bits == 64 ? kShapes64 : kShapes32;
     c.block_threads = shapes[i / kNumLimits][0];
     c.items_per_thread = shapes[i / kNumLimits][1];

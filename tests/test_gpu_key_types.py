@@ -179,3 +179,18 @@ def test_typed_large_float_pairs(ow):
     bits = W.float_bits(23, n, 32)
     check(ow, bits, "float", np.arange(n, dtype=np.uint32), descending=True)
     check(ow, bits, "float", None, descending=False)
+
+
+def test_typed_segmented_tuner_keeps_the_key_order(ow):
+    lengths = np.array(EDGE_LENGTHS, dtype=np.int64)
+    off = W.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    bits = bits_of("float", 29, n, 32)
+    v = np.arange(n, dtype=np.uint32)
+    t = dev(bits.view(np.float32))
+    cfg = ow.tune_segments(t, dev(off.astype(np.uint32)), dev(v), keys_out=None,
+                           repetitions=1, descending=True)
+    assert cfg.key_type == ow.KEY_FLOAT and cfg.descending == 1
+    ko, vo = ow.sort_segments(dev(bits), dev(off.astype(np.uint32)), dev(v), config=cfg)
+    wk, wv = oracle.sort_segments(bits, off, v, key_type=oracle.KEY_FLOAT, descending=True)
+    assert np.array_equal(ko.cpu().numpy(), wk) and np.array_equal(vo.cpu().numpy(), wv)
