@@ -375,8 +375,9 @@ onesweep_status_t onesweep_model_train_step(onesweep_model_t *model, const float
  * single kernel, the best class that applies to key_bits, then a
  * synchronisation of `stream` to read the choice (written by the kernel to
  * pinned host memory). A NULL model (or n == 0) yields the library default
- * (all fields 0). cfg_out->trace is NULL. Calls on one model must not
- * overlap. */
+ * (fields 0). cfg_out->key_type and cfg_out->descending are read on input
+ * and kept (the features see the raw key bits); cfg_out->trace is NULL.
+ * Calls on one model must not overlap. */
 onesweep_status_t onesweep_select_config(const onesweep_model_t *model, const void *d_keys,
                                          size_t n, int key_bits, int begin_bit, int end_bit,
                                          int has_values, onesweep_config_t *cfg_out,

@@ -513,10 +513,11 @@ class Model:
 
 def select_config(model: Model | None, keys: torch.Tensor, begin_bit: int = 0,
                   end_bit: int | None = None, has_values: bool = False, stream=None) -> Config:
-    """Configuration the model picks for these keys (synchronises the stream)."""
+    """Configuration the model picks for these keys (synchronises the stream);
+    it keeps the key type of the keys' dtype."""
     kb = _key_bits(keys)
     end_bit = kb if end_bit is None else end_bit
-    cfg = Config()
+    cfg = _ordered_config(None, keys, False) or Config()
     _check(_lib.onesweep_select_config(None if model is None else model.handle, _dev_ptr(keys),
                                        keys.numel(), kb, begin_bit, end_bit, int(has_values),
                                        ctypes.byref(cfg), _stream(stream)))

@@ -475,8 +475,15 @@ onesweep_status_t onesweep_select_config(const onesweep_model_t *m, const void *
   if (!cfg_out) return fail(ONESWEEP_ERROR_INVALID_VALUE, "cfg_out is NULL");
   if (key_bits != 32 && key_bits != 64)
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "key_bits %d is not 32 or 64", key_bits);
+  // The key order is the caller's and is kept; everything else is chosen.
+  const int key_type = cfg_out->key_type, descending = cfg_out->descending;
+  auto keep_order = [&](onesweep_status_t st) {
+    cfg_out->key_type = key_type;
+    cfg_out->descending = descending;
+    return st;
+  };
   memset(cfg_out, 0, sizeof(*cfg_out));
-  if (!m || n == 0) return ONESWEEP_SUCCESS;  // the library's default configuration
+  if (!m || n == 0) return keep_order(ONESWEEP_SUCCESS);  // the library's default
   if (begin_bit < 0 || begin_bit > end_bit || end_bit > key_bits)
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "bit range [%d, %d) invalid", begin_bit, end_bit);
   if (!d_keys || (reinterpret_cast<uintptr_t>(d_keys) & (key_bits / 8 - 1)))
@@ -501,8 +508,8 @@ onesweep_status_t onesweep_select_config(const onesweep_model_t *m, const void *
   MLP_TRY(launch_select(key_bits, a, s), "select");
   MLP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   const int choice = *static_cast<volatile int *>(m->host_choice);
-  if (choice < 0 || choice >= kMlpClasses) return ONESWEEP_SUCCESS;  // no class applies
-  return onesweep_model_class(m, choice, cfg_out, nullptr);
+  if (choice < 0 || choice >= kMlpClasses) return keep_order(ONESWEEP_SUCCESS);  // none applies
+  return keep_order(onesweep_model_class(m, choice, cfg_out, nullptr));
 }
 
 }  // extern "C"

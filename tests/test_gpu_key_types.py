@@ -194,3 +194,17 @@ def test_typed_segmented_tuner_keeps_the_key_order(ow):
     ko, vo = ow.sort_segments(dev(bits), dev(off.astype(np.uint32)), dev(v), config=cfg)
     wk, wv = oracle.sort_segments(bits, off, v, key_type=oracle.KEY_FLOAT, descending=True)
     assert np.array_equal(ko.cpu().numpy(), wk) and np.array_equal(vo.cpu().numpy(), wv)
+
+
+def test_learned_selection_keeps_the_key_type(ow):
+    """The committed model's pick for float keys keeps the float order."""
+    import os
+    model = ow.Model(max_batch=1, path=os.path.join(os.path.dirname(ow.__file__),
+                                                    "config_model.bin"))
+    n = (1 << 20) + 17
+    bits = bits_of("float", 31, n, 32)
+    t = dev(bits.view(np.float32))
+    cfg = ow.select_config(model, t)
+    assert cfg.key_type == ow.KEY_FLOAT
+    check(ow, bits, "float", None, config=cfg)
+    check(ow, bits, "float", np.arange(n, dtype=np.uint32), descending=True, config=cfg)
