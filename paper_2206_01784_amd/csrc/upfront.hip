@@ -54,28 +54,49 @@ __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
 
   const uint32_t n = a.n;
   const bool aligned = (reinterpret_cast<uintptr_t>(a.keys) & 15u) == 0u;
-  for (uint32_t base = blockIdx.x * kTile; base < n; base += gridDim.x * kTile) {
-    if (aligned && base + kTile <= n) {
+  const uint32_t stride = gridDim.x * static_cast<uint32_t>(kTile);
+  uint32_t base = blockIdx.x * static_cast<uint32_t>(kTile);
+  auto count_vec = [&](const uint4 &q) {
+    if constexpr (sizeof(K) == 4) {
+      count_key(q.x);
+      count_key(q.y);
+      count_key(q.z);
+      count_key(q.w);
+    } else {
+      count_key(static_cast<K>(q.x) | (static_cast<K>(q.y) << 32));
+      count_key(static_cast<K>(q.z) | (static_cast<K>(q.w) << 32));
+    }
+  };
+  if (aligned) {
+    // Whole tiles, software-pipelined: the next tile's loads are in flight
+    // while this one is counted (n < 2^31 keeps base + stride from wrapping).
+    auto whole = [&](uint32_t b) { return b < n && n - b >= static_cast<uint32_t>(kTile); };
+    uint4 q[kVec];
+    if (whole(base)) {
       const uint4 *v = reinterpret_cast<const uint4 *>(a.keys + base);
-      uint4 q[kVec];
 #pragma unroll
       for (int i = 0; i < kVec; ++i) q[i] = v[i * kBlock + tid];
-#pragma unroll
-      for (int i = 0; i < kVec; ++i) {
-        if constexpr (sizeof(K) == 4) {
-          count_key(q[i].x);
-          count_key(q[i].y);
-          count_key(q[i].z);
-          count_key(q[i].w);
-        } else {
-          count_key(static_cast<K>(q[i].x) | (static_cast<K>(q[i].y) << 32));
-          count_key(static_cast<K>(q[i].z) | (static_cast<K>(q[i].w) << 32));
-        }
-      }
-    } else {
-      const uint32_t end = min(n, base + static_cast<uint32_t>(kTile));
-      for (uint32_t i = base + tid; i < end; i += kBlock) count_key(a.keys[i]);
     }
+    while (whole(base)) {
+      uint4 cur[kVec];
+#pragma unroll
+      for (int i = 0; i < kVec; ++i) cur[i] = q[i];
+      const uint32_t next = base + stride;
+      if (whole(next)) {
+        const uint4 *v = reinterpret_cast<const uint4 *>(a.keys + next);
+#pragma unroll
+        for (int i = 0; i < kVec; ++i) q[i] = v[i * kBlock + tid];
+      }
+#pragma unroll
+      for (int i = 0; i < kVec; ++i) count_vec(cur[i]);
+      base = next;
+    }
+  }
+  // The last, partial tile (or every tile when the keys are not 16-byte
+  // aligned), one key per thread at a time.
+  for (; base < n; base += stride) {
+    const uint32_t end = min(n, base + static_cast<uint32_t>(kTile));
+    for (uint32_t i = base + tid; i < end; i += kBlock) count_key(a.keys[i]);
   }
   __syncthreads();
   for (int i = tid; i < places * kRadix; i += kBlock) {
