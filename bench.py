@@ -686,6 +686,16 @@ def main():
     value = n / (ms_per_step * 1e-3) / 1e9
     log(f"[bench] {steps} steps in {ms_total:.3f} ms (wall {wall * 1e3:.1f} ms)")
 
+    # Per-step durations (first launch's start to last launch's end of each
+    # step, from the traced events): median, min and interquartile range.
+    step_ms = sorted(evs[0].elapsed_time(evs[2 * tr.count - 1]) for tr, evs, _ in holders
+                     if tr.count > 0)
+    q = lambda f: step_ms[min(len(step_ms) - 1, int(f * (len(step_ms) - 1) + 0.5))]  # noqa: E731
+    step_stats = {"median_ms": round(q(0.5), 4), "min_ms": round(step_ms[0], 4),
+                  "iqr_ms": round(q(0.75) - q(0.25), 4)}
+    log(f"[bench] per step: median {step_stats['median_ms']} ms, min {step_stats['min_ms']} ms, "
+        f"IQR {step_stats['iqr_ms']} ms")
+
     # Per-kernel durations from the traced events.
     per_kind = per_kind_times(holders)
     for kind, ts in sorted(per_kind.items()):
@@ -714,6 +724,25 @@ def main():
     whole_gbs = sort_bytes / (ms_per_step * 1e-3) / 1e9
     log(f"[bench] whole sort: {whole_gbs:.1f} GB/s algorithmic = {whole_gbs / HBM_PEAK_GBS:.3f} "
         f"of peak; binning: {achieved:.1f} GB/s")
+    # Context: the library's plain copy kernel on the same buffers (an empty
+    # bit range sorts nothing), timed after the sort steps.
+    def copy_once():
+        if has_vals:
+            ow.sort_pairs(d_keys, d_vals, 0, 0, keys_out=d_kout, values_out=d_vout, temp=temp,
+                          stream=stream)
+        else:
+            ow.sort_keys(d_keys, 0, 0, out=d_kout, temp=temp, stream=stream)
+    copy_once()
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        copy_once()
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * n * (kb + vb) / (c0.elapsed_time(c1) / 5 * 1e-3) / 1e9
+    log(f"[bench] copy kernel: {copy_gbs:.1f} GB/s; whole sort at "
+        f"{whole_gbs / copy_gbs:.3f} of it, binning at {achieved / copy_gbs:.3f}")
 
     result = {
         "metric": METRIC,
@@ -738,6 +767,9 @@ def main():
             "key_type": key_kind, "descending": descending,
             "tile": ow.tile_items(key_bits, has_vals, cfg_plain, n),
             "hbm_fraction_whole_sort": round(whole_gbs / HBM_PEAK_GBS, 4),
+            "copy_kernel_gbs": round(copy_gbs, 1),
+            "whole_sort_over_copy": round(whole_gbs / copy_gbs, 4),
+            "per_step": step_stats,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
