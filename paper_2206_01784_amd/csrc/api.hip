@@ -103,7 +103,8 @@ enum Caller { kCallSort, kCallSegments, kCallOther };
 
 onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const onesweep_config_t *cfg,
                           Resolved *r, Caller caller = kCallOther) {
-  r->shape = binning_default_shape(key_bits, has_values, n);
+  r->shape = caller == kCallSegments ? segment_default_shape(key_bits, has_values)
+                                     : binning_default_shape(key_bits, has_values, n);
   r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
   r->algorithm = ONESWEEP_ALGORITHM_ONESWEEP;
   r->strip_log2 = kDefaultStripLog2;

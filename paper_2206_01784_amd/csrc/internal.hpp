@@ -36,6 +36,7 @@ enum BinningMode : int { kBinChained = 0, kBinSegmented = 1, kBinDownsweep = 2 }
 
 bool binning_shape_supported(const BinningShape &s, int mode);
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n);
+BinningShape segment_default_shape(int key_bits, bool has_values);
 // Keys per binning tile of a shape.
 size_t binning_tile_items(const BinningShape &s);
 
