@@ -52,19 +52,47 @@ __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
     }
   };
 
+  // 32-bit keys: a wave whose 64 keys are all equal (constant or nearly
+  // constant inputs) adds 64 to one counter per place from its first lane
+  // instead of 64 same-address atomics per place; the test is one ballot per
+  // key (measured: all-equal keys 437 -> 248 us at 2^28, uniform keys
+  // unchanged, AND-skewed keys +4-7%; 64-bit keys lost 28% and skip it).
+  const bool wave_leader = (tid & (kWave - 1)) == 0;
+  auto count_key_wave = [&](K k) {
+    if constexpr (sizeof(K) != 4) {
+      count_key(k);
+      return;
+    }
+    const K k0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(k));
+    if (__ballot(k != k0) == 0ull) {
+      if (wave_leader) {
+        const K t = kOrdered ? ordered_bits(k0, a.order) : k0;
+#pragma unroll
+        for (int j = 0; j < kMaxP; ++j) {
+          if (j < places) {
+            const uint32_t d = static_cast<uint32_t>(t >> shifts[j]) & masks[j];
+            atomicAdd(&my_hist[(j * kRadix + d) * kCopies], static_cast<uint32_t>(kWave));
+          }
+        }
+      }
+    } else {
+      count_key(k);
+    }
+  };
+
   const uint32_t n = a.n;
   const bool aligned = (reinterpret_cast<uintptr_t>(a.keys) & 15u) == 0u;
   const uint32_t stride = gridDim.x * static_cast<uint32_t>(kTile);
   uint32_t base = blockIdx.x * static_cast<uint32_t>(kTile);
-  auto count_vec = [&](const uint4 &q) {
+  auto count_vec = [&](const uint4 &q) {  // whole tiles: every lane active
     if constexpr (sizeof(K) == 4) {
-      count_key(q.x);
-      count_key(q.y);
-      count_key(q.z);
-      count_key(q.w);
+      count_key_wave(q.x);
+      count_key_wave(q.y);
+      count_key_wave(q.z);
+      count_key_wave(q.w);
     } else {
-      count_key(static_cast<K>(q.x) | (static_cast<K>(q.y) << 32));
-      count_key(static_cast<K>(q.z) | (static_cast<K>(q.w) << 32));
+      count_key_wave(static_cast<K>(q.x) | (static_cast<K>(q.y) << 32));
+      count_key_wave(static_cast<K>(q.z) | (static_cast<K>(q.w) << 32));
     }
   };
   if (aligned) {

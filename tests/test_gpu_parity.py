@@ -48,6 +48,19 @@ def test_histogram_parity(ow, kb, dist, n):
         assert np.array_equal(got, want), (dist, n, begin, end)
 
 
+@pytest.mark.parametrize("kb", [32, 64])
+def test_histogram_of_constant_runs(ow, kb):
+    """Runs of equal keys (of 64, 100 and 4096 keys, some aligned with
+    waves, some not) mix waves whose keys are all equal with mixed waves."""
+    n = 3 * 65536 + 77
+    for run in (64, 100, 4096):
+        keys = W.runs(37 + run, n, kb, run=run, low_bits=0)
+        for begin, end in [(0, kb), (5, kb - 3)]:
+            got = host(ow.histogram(dev(keys), begin, end)).astype(np.uint64)
+            assert np.array_equal(got, oracle.histograms(keys, begin, end, 8)), (run, begin)
+        check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb)
+
+
 def test_histogram_empty_and_unaligned(ow):
     h = ow.histogram(torch.empty(0, dtype=torch.uint32, device="cuda"))
     assert host(h).sum() == 0
