@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libonesweep.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first "
-        "(python paper_2206_01784_amd/build.py, or __graft_entry__.build())")
+        "(python paper_2206_01784_amd/build.py)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
