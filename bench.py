@@ -605,12 +605,12 @@ def main():
     algorithm = (ow.ALGORITHM_REDUCE_THEN_SCAN if args.algorithm == "reduce-then-scan"
                  else ow.ALGORITHM_ONESWEEP)
 
-    # Onesweep bins inputs above 2^28 keys in strips: one launch per strip
-    # and place (each strip at most 2^28 keys, whole tiles).
+    # Onesweep bins inputs above 2^29 keys in strips: one launch per strip
+    # and place (each strip at most 2^29 keys, whole tiles).
     tile = ow.tile_items(key_bits, has_vals, ow.make_config(args.block, args.ipt,
                                                            rank_algorithm=args.rank), n)
     tiles = -(-n // tile)
-    strips = -(-tiles // max(1, (1 << 28) // tile))
+    strips = -(-tiles // max(1, (1 << 29) // tile))
 
     def traced_configs(alg, count):
         """`count` configs, each recording HIP events around every launch on

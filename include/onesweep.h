@@ -36,7 +36,7 @@
  *  - The chained-scan status words hold 30-bit values (Section 3, "Handling
  *    very large problems"): one chained scan covers fewer than 2^30 keys.
  *    Whole plain sorts (onesweep_sort_keys/pairs) bin large inputs in strips
- *    of at most 2^28 keys and accept n below 2^31; the other entry points
+ *    of at most 2^29 keys and accept n below 2^31; the other entry points
  *    accept n below 2^30. Larger n returns ONESWEEP_ERROR_TOO_LARGE.
  *  - Errors are returned as status codes; nothing is enqueued when argument
  *    validation fails. onesweep_last_error() describes the last failure of
@@ -162,8 +162,8 @@ typedef struct {
                                 (whole tiles, at least one), each strip its own
                                 chained scan whose last tile hands the next strip its
                                 bin starts (Section 3, handling very large problems).
-                                0 = 28, the default; else 11..28. Smaller strips only
-                                serve tests of inputs below 2^28. */
+                                0 = 29, the default; else 11..29. Smaller strips only
+                                serve tests of inputs below 2^29. */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 

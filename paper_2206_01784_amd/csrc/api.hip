@@ -35,11 +35,13 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxN = size_t(1) << 30;  // 30-bit status values, one chained scan
-// Whole plain sorts run large inputs as strips of at most 2^28 keys per
+// Whole plain sorts run large inputs as strips of at most 2^29 keys per
 // binning pass (each strip its own chained scan), so 30-bit status values
 // never overflow; 32-bit element indices keep a factor-2 headroom below 2^31.
+// (2^29 rather than the paper's 2^28: tiles of 1024 x 11 keys do not divide
+// 2^28, and a 2^28-key sort should stay one strip.)
 constexpr size_t kMaxSortN = size_t(1) << 31;
-constexpr int kDefaultStripLog2 = 28;
+constexpr int kDefaultStripLog2 = 29;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 

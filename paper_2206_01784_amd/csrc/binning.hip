@@ -58,15 +58,15 @@ constexpr bool kCheckedStores = ONESWEEP_CHECKED_STORES != 0;
 // Predecessor tiles read per look-back round trip.
 constexpr int kLookback = ONESWEEP_LOOKBACK_WINDOW;
 
-// Occupancy target (waves per SIMD the register allocation must allow):
-// as high as the key registers permit without spilling. 64-bit keys at 8
-// per thread still fit 64 registers (8 waves per SIMD, two 1024-thread
-// workgroups per CU); 32-bit keys at 16 per thread would spill there.
-template <typename K, int kIpt>
+// Occupancy target (waves per SIMD the register allocation must allow).
+// 1024-thread workgroups always take 8 (64 registers): two of them per CU
+// keep twice the keys in flight of one, which outweighs a few spilled
+// registers (32-bit keys at 11 per thread spill 8 bytes and are the fastest
+// shape at 2^28 keys; at occupancy 6 only one such workgroup fits a CU).
+// Smaller workgroups: as high as the key registers permit without spilling.
+template <typename K, int kBlock, int kIpt>
 constexpr int binning_waves_per_eu() {
-  return (kIpt * sizeof(K)) <= 32 || (sizeof(K) == 8 && kIpt == 8)
-             ? 8
-             : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
+  return kBlock == 1024 || (kIpt * sizeof(K)) <= 32 ? 8 : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
 }
 
 // kMode: kBinChained, one sequence with a chained scan over its tiles;
@@ -78,7 +78,7 @@ constexpr int binning_waves_per_eu() {
 // descending order); false for unsigned ascending sorts.
 template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode, bool kOrdered>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(binning_waves_per_eu<K, kIpt>())))
+    __attribute__((amdgpu_waves_per_eu(binning_waves_per_eu<K, kBlock, kIpt>())))
     binning_kernel(BinningArgs<K> a) {
   constexpr bool kSeg = kMode == kBinSegmented;
   constexpr bool kRts = kMode == kBinDownsweep;
@@ -441,6 +441,24 @@ __global__ void __launch_bounds__(kBlock)
   X(uint32_t, false, 512, 16, 0)      \
   X(uint32_t, false, 512, 12, 0)      \
   X(uint32_t, false, 1024, 8, 0)      \
+  X(uint32_t, false, 1024, 10, 0)     \
+  X(uint32_t, false, 1024, 11, 0)     \
+  X(uint32_t, false, 1024, 10, 1)     \
+  X(uint32_t, false, 1024, 11, 1)     \
+  X(uint32_t, false, 1024, 10, 2)     \
+  X(uint32_t, false, 1024, 11, 2)     \
+  X(uint32_t, true, 1024, 10, 0)      \
+  X(uint32_t, true, 1024, 11, 0)      \
+  X(uint32_t, true, 1024, 10, 1)      \
+  X(uint32_t, true, 1024, 11, 1)      \
+  X(uint32_t, true, 1024, 10, 2)      \
+  X(uint32_t, true, 1024, 11, 2)      \
+  X(uint64_t, false, 1024, 9, 0)      \
+  X(uint64_t, false, 1024, 9, 1)      \
+  X(uint64_t, false, 1024, 9, 2)      \
+  X(uint64_t, true, 1024, 9, 0)       \
+  X(uint64_t, true, 1024, 9, 1)       \
+  X(uint64_t, true, 1024, 9, 2)       \
   X(uint32_t, false, 256, 16, 1)      \
   X(uint32_t, false, 512, 16, 1)      \
   X(uint32_t, false, 512, 12, 1)      \
@@ -518,6 +536,9 @@ __global__ void __launch_bounds__(kBlock)
   X(uint32_t, true, 512, 16, 0)      \
   X(uint32_t, false, 1024, 8, 0)     \
   X(uint32_t, true, 1024, 8, 0)      \
+  X(uint32_t, false, 1024, 11, 0)    \
+  X(uint32_t, true, 1024, 11, 0)     \
+  X(uint64_t, false, 1024, 9, 0)     \
   X(uint64_t, false, 256, 8, 0)      \
   X(uint64_t, true, 256, 8, 0)       \
   X(uint64_t, false, 512, 8, 0)      \
@@ -542,24 +563,28 @@ bool binning_shape_supported(const BinningShape &s, int mode) {
   return false;
 }
 
-// The autotuned plain configuration: the fastest tile shape per key width,
-// value presence and input size, from 1000 timing records of every built
-// shape over the seeded sweep of sizes 2^17..2^28 on MI355X (plus the
-// full-size benchmarks for 2^27 and more). Small inputs want more, smaller
-// tiles to fill 256 CUs; from 2^18-2^19 keys on, 1024 x 8 wins except for
-// 32-bit pairs at 2^27 and more, where 512 x 16 is as fast or faster.
 size_t binning_tile_items(const BinningShape &s) {
   return static_cast<size_t>(s.block) * static_cast<size_t>(s.ipt);
 }
 
+// The autotuned plain configuration: the fastest tile shape per key width,
+// value presence and input size, measured on MI355X over uniform inputs of
+// 2^18..2^28 keys (and the seeded sweep of 2^17..2^28). Small inputs want
+// more, smaller tiles to fill 256 CUs; from 2^21 keys on, the largest tile
+// that two 1024-thread workgroups per CU can hold wins: 32-bit keys and pairs
+// 1024 x 11 (2^28 keys: 3.24 against 3.63 ms with 1024 x 8; pairs 5.37
+// against 5.54 with 512 x 16), 64-bit keys 1024 x 9 (3% faster than
+// 1024 x 8); 64-bit pairs stay at 1024 x 8.
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
+  const bool large = n >= (size_t(1) << 21);
   if (key_bits == 64) {
     if (has_values && n < (size_t(3) << 16)) return BinningShape{64, true, 256, 8, kRankBallot};
     if (n < (size_t(1) << 19)) return BinningShape{64, has_values, 512, 8, kRankBallot};
+    if (large && !has_values) return BinningShape{64, false, 1024, 9, kRankBallot};
     return BinningShape{64, has_values, 1024, 8, kRankBallot};
   }
   if (n < (size_t(1) << 18)) return BinningShape{32, has_values, 256, 8, kRankBallot};
-  if (has_values && n >= (size_t(1) << 27)) return BinningShape{32, true, 512, 16, kRankBallot};
+  if (large) return BinningShape{32, has_values, 1024, 11, kRankBallot};
   return BinningShape{32, has_values, 1024, 8, kRankBallot};
 }
 

@@ -144,7 +144,7 @@ def test_key_type_and_direction_validation_needs_no_gpu():
 
 
 def test_strip_configuration_and_size_limits_need_no_gpu():
-    """Whole plain sorts accept n up to 2^31 - 1 (strips of at most 2^28
+    """Whole plain sorts accept n up to 2^31 - 1 (strips of at most 2^29
     keys per chained scan); the single-pass, histogram and segmented entry
     points keep one chained scan and the 2^30 limit."""
     import paper_2206_01784_amd as ow
@@ -158,7 +158,7 @@ def test_strip_configuration_and_size_limits_need_no_gpu():
     one = ow.sort_temp_bytes(1 << 20, 32)
     strips = ow.sort_temp_bytes(1 << 20, 32, config=ow.make_config(strip_log2=14))
     assert strips - one >= (64 - 1) * 256 * 4
-    for bad in (10, 29, -1):
+    for bad in (10, 30, -1):
         cfg = ow.make_config(strip_log2=bad)
         rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
                                     ctypes.byref(cfg), None)

@@ -74,10 +74,10 @@ def test_histogram_empty_and_unaligned(ow):
 # ------------------------------------------------------------------ phase 3 (one pass)
 
 SHAPES = {
-    (32, False): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8)],
-    (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8)],
-    (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8)],
-    (64, True): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8)],
+    (32, False): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11)],
+    (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11)],
+    (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
+    (64, True): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
 }
 RANKS = (1, 2, 3)  # one ballot per digit bit; LDS presence masks; ballots + LDS atomics
 
@@ -283,7 +283,7 @@ def test_graph_capture_replays(ow):
 # ------------------------------------------------------------------ reduce-then-scan baseline
 
 RTS_SHAPES = {
-    32: [(256, 8), (512, 16), (1024, 8)],
+    32: [(256, 8), (512, 16), (1024, 8), (1024, 11)],
     64: [(256, 8), (512, 8), (1024, 8)],
 }
 
