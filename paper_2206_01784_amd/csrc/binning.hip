@@ -525,7 +525,11 @@ __global__ void __launch_bounds__(kBlock)
   X(uint64_t, false, 1024, 8, 0)           \
   X(uint64_t, true, 256, 16, 0)            \
   X(uint64_t, true, 512, 8, 0)             \
-  X(uint64_t, true, 1024, 8, 0)
+  X(uint64_t, true, 1024, 8, 0)            \
+  X(uint32_t, false, 1024, 11, 0)          \
+  X(uint32_t, true, 1024, 11, 0)           \
+  X(uint64_t, false, 1024, 9, 0)           \
+  X(uint64_t, true, 1024, 9, 0)
 
 // Shapes built for the reduce-then-scan baseline (ballot ranking): the
 // default shapes of every key width and value presence.
@@ -590,11 +594,14 @@ BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
 
 // The default tile shape of the segmented sort's large segments, measured on
 // MI355X with the batched workload (20000 log-normal segments, 2^26 keys,
-// graph replay): 32-bit keys 256 x 16 (0.865 ms against 0.911 with 1024 x 8),
-// 32-bit pairs 512 x 16 (1.198 against 1.293), 64-bit keys and pairs
-// 1024 x 8 (2.30 and 3.11 ms, the fastest of the built shapes).
+// graph replay): 32-bit keys 256 x 16 (0.87-0.90 ms against 0.91 with
+// 1024 x 8 and 0.92 with 1024 x 11), 32-bit pairs 512 x 16 (1.20 against
+// 1.29 and 1.25), 64-bit keys 1024 x 9 (2.25 against 2.33 with 1024 x 8),
+// 64-bit pairs 1024 x 8 (3.11, as fast as 1024 x 9).
 BinningShape segment_default_shape(int key_bits, bool has_values) {
-  if (key_bits == 64) return BinningShape{64, has_values, 1024, 8, kRankBallot};
+  if (key_bits == 64)
+    return has_values ? BinningShape{64, true, 1024, 8, kRankBallot}
+                      : BinningShape{64, false, 1024, 9, kRankBallot};
   return has_values ? BinningShape{32, true, 512, 16, kRankBallot}
                     : BinningShape{32, false, 256, 16, kRankBallot};
 }
