@@ -25,12 +25,14 @@ struct ModelClass {
   int hist_blocks_per_cu;
 };
 
-// Classes of a freshly created model: every binning tile shape built for the
-// plain sort, with both ranking methods.
+// Classes of a freshly created model: the plain sort's tile shapes with
+// ballot ranking (the 1024-thread tiles of 9-11 keys per thread included),
+// and presence-mask ranking for the smallest and the 1024-thread tiles.
+// (key-width mask 1 = 32-bit, 2 = 64-bit, 3 = both; rank 1 ballots, 2 masks.)
 constexpr ModelClass kDefaultClasses[kMlpClasses] = {
-    {3, 256, 8, 1, 0},  {3, 256, 8, 2, 0},  {3, 256, 16, 1, 0}, {3, 256, 16, 2, 0},
-    {2, 512, 8, 1, 0},  {2, 512, 8, 2, 0},  {3, 512, 12, 1, 0}, {3, 512, 12, 2, 0},
-    {1, 512, 16, 1, 0}, {1, 512, 16, 2, 0}, {3, 1024, 8, 1, 0}, {3, 1024, 8, 2, 0}};
+    {3, 256, 8, 1, 0},    {3, 256, 16, 1, 0},  {2, 512, 8, 1, 0},   {3, 512, 12, 1, 0},
+    {1, 512, 16, 1, 0},   {3, 1024, 8, 1, 0},  {1, 1024, 10, 1, 0}, {1, 1024, 11, 1, 0},
+    {2, 1024, 9, 1, 0},   {3, 256, 8, 2, 0},   {3, 1024, 8, 2, 0},  {1, 1024, 11, 2, 0}};
 
 constexpr char kMagic[8] = {'O', 'S', 'W', 'M', 'L', 'P', '0', '1'};
 
