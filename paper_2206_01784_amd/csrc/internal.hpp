@@ -67,7 +67,6 @@ hipError_t launch_tile_scan(uint32_t *counts, uint32_t tiles, const PassPlan *pl
                             hipStream_t stream);
 
 // Histogram of all places (phase 1), persistent tile-cyclic grid.
-constexpr int kHistBlock = 256;
 hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint32_t n,
                             int begin_bit, int end_bit, int places, const KeyOrder &order,
                             uint32_t grid, hipStream_t stream);

@@ -55,8 +55,9 @@ __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
   // 32-bit keys: a wave whose 64 keys are all equal (constant or nearly
   // constant inputs) adds 64 to one counter per place from its first lane
   // instead of 64 same-address atomics per place; the test is one ballot per
-  // key (measured: all-equal keys 437 -> 248 us at 2^28, uniform keys
-  // unchanged, AND-skewed keys +4-7%; 64-bit keys lost 28% and skip it).
+  // key (measured with 8 copies in 256-thread workgroups: all-equal keys
+  // 437 -> 248 us at 2^28, uniform keys unchanged, AND-skewed keys +4-7%;
+  // 64-bit keys lost 28% and skip it).
   const bool wave_leader = (tid & (kWave - 1)) == 0;
   auto count_key_wave = [&](K k) {
     if constexpr (sizeof(K) != 4) {
@@ -135,8 +136,17 @@ __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
   }
 }
 
-constexpr int kHistVec = 4;     // uint4 loads per thread per tile
-constexpr int kHistCopies = 8;  // interleaved LDS copies per counter
+// Workgroup shape: 1024 threads, two workgroups (32 waves) per CU. 32-bit
+// keys keep 16 interleaved copies of their 4 x 256 counters (64 KiB of LDS),
+// 64-bit keys 8 copies of 8 x 256 (64 KiB). Measured at 2^28 32-bit keys
+// against 256-thread workgroups with 8 copies: uniform 251 -> 205 us, AND of
+// 4 words 451 -> 238 us, all equal 246 -> 214 us; 16 copies in 256-thread
+// workgroups (8 waves per CU) were slower (343 us); 2^27 64-bit keys
+// 249 -> 230 us.
+constexpr int kHistVec = 4;  // uint4 loads per thread per tile
+constexpr int kHistBlock = 1024;
+constexpr int kHistCopies32 = 16;
+constexpr int kHistCopies64 = 8;
 
 hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint32_t n,
                             int begin_bit, int end_bit, int places, const KeyOrder &order,
@@ -145,19 +155,19 @@ hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint
     HistogramArgs<uint32_t> a{static_cast<const uint32_t *>(keys), hist, n, begin_bit, end_bit,
                               places, order};
     if (key_order_is_plain(order))
-      hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies, false>),
+      hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies32, false>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
     else
-      hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies, true>),
+      hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies32, true>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
   } else {
     HistogramArgs<uint64_t> a{static_cast<const uint64_t *>(keys), hist, n, begin_bit, end_bit,
                               places, order};
     if (key_order_is_plain(order))
-      hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies, false>),
+      hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies64, false>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
     else
-      hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies, true>),
+      hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies64, true>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
   }
   return hipGetLastError();
