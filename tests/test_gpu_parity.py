@@ -61,6 +61,24 @@ def test_histogram_of_constant_runs(ow, kb):
         check_sort(ow, keys, np.arange(n, dtype=np.uint32), 0, kb)
 
 
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("dist", ["uniform", "and4"])
+def test_histogram_several_trips_per_workgroup(ow, kb, dist):
+    """A one-workgroup-per-CU grid over more keys than one sweep of it covers:
+    each workgroup walks several whole tiles with the next tile's loads in
+    flight, then the ragged tail; also the 16-byte-unaligned scalar path."""
+    per_sweep = 256 * 1024 * 4 * 16 // (kb // 8)  # CUs x threads x 4 loads x 16 B / key bytes
+    n = 2 * per_sweep + 3 * 4099
+    keys = keys_of(dist, 43, n, kb)
+    cfg = ow.make_config(hist_blocks_per_cu=1)
+    t = dev(keys)
+    for begin, end in [(0, kb), (6, kb - 2)]:
+        got = host(ow.histogram(t, begin, end, config=cfg)).astype(np.uint64)
+        assert np.array_equal(got, oracle.histograms(keys, begin, end, 8)), (begin, end)
+    got = host(ow.histogram(t[1:], config=cfg)).astype(np.uint64)
+    assert np.array_equal(got, oracle.histograms(keys[1:], 0, kb, 8))
+
+
 def test_histogram_empty_and_unaligned(ow):
     h = ow.histogram(torch.empty(0, dtype=torch.uint32, device="cuda"))
     assert host(h).sum() == 0
