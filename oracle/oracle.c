@@ -320,15 +320,12 @@ int oracle_sort_segments(const void *keys_in, const uint32_t *vals_in, void *key
 }
 
 /*
- * Final state of one chained-scan binning pass (Section 3, Figures 6 and 7f):
- * with the input cut into tiles of `tile` consecutive elements, every status
- * counter ends as status G holding the inclusive prefix, over this and all
- * earlier tiles, of the number of elements with that digit. The value is kept
- * modulo 2^30 as the 30-bit field stores it; callers keep n below 2^30.
- * status[t * 2^width + v] for tile t and digit v.
+ * Segmented sort of keys of any type and direction: the typed stable sort
+ * (oracle_sort_typed) applied independently to every segment
+ * [seg_off[s], seg_off[s+1]), with the same offset rules as
+ * oracle_sort_segments. Not in the paper; defined as that per-segment
+ * application.
  */
-/* Segmented sort of keys of any type and direction: oracle_sort_typed per
- * segment. */
 int oracle_sort_segments_typed(const void *keys_in, const uint32_t *vals_in, void *keys_out,
                                uint32_t *vals_out, int key_bits, size_t n,
                                const uint64_t *seg_off, size_t num_segments, int begin_bit,
@@ -351,6 +348,14 @@ int oracle_sort_segments_typed(const void *keys_in, const uint32_t *vals_in, voi
     return ORACLE_OK;
 }
 
+/*
+ * Final state of one chained-scan binning pass (Section 3, Figures 6 and 7f):
+ * with the input cut into tiles of `tile` consecutive elements, every status
+ * counter ends as status G holding the inclusive prefix, over this and all
+ * earlier tiles, of the number of elements with that digit. The value is kept
+ * modulo 2^30 as the 30-bit field stores it; callers keep n below 2^30.
+ * status[t * 2^width + v] for tile t and digit v.
+ */
 int oracle_pass_status(const void *src_keys, int key_bits, size_t n, int lo, int width,
                        size_t tile, uint32_t *status)
 {

@@ -47,6 +47,19 @@ MUTANTS = {
     "typed_gather_keeps_input_order": (
         "store_key(keys_out, key_bits, i, load_key(keys_in, key_bits, idx_out[i]));",
         "store_key(keys_out, key_bits, i, load_key(keys_in, key_bits, i));"),
+    "segments_typed_sorts_raw_bits": (
+        "        rc = oracle_sort_typed((const char *)keys_in + a * kb, vals_in ? vals_in + a : NULL,\n"
+        "                               (char *)keys_out + a * kb, vals_out ? vals_out + a : NULL,\n"
+        "                               key_bits, len, begin_bit, end_bit, d, key_type, descending);",
+        "        rc = oracle_sort((const char *)keys_in + a * kb, vals_in ? vals_in + a : NULL,\n"
+        "                         (char *)keys_out + a * kb, vals_out ? vals_out + a : NULL,\n"
+        "                         key_bits, len, begin_bit, end_bit, d, NULL);"),
+    "segments_typed_values_not_offset": (
+        "        rc = oracle_sort_typed((const char *)keys_in + a * kb, vals_in ? vals_in + a : NULL,",
+        "        rc = oracle_sort_typed((const char *)keys_in + a * kb, vals_in ? vals_in : NULL,"),
+    "segments_typed_direction_dropped": (
+        "key_bits, len, begin_bit, end_bit, d, key_type, descending);",
+        "key_bits, len, begin_bit, end_bit, d, key_type, 0);"),
 }
 
 

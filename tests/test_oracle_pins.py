@@ -403,3 +403,72 @@ def test_descending_unsigned_sort_brute_force(kb):
     field = lambda i: (int(k[i]) >> b) & ((1 << (e - b)) - 1)  # noqa: E731
     ko, vo = oracle.sort(k, v, b, e, descending=True)
     assert list(vo) == sorted(range(k.size), key=lambda i: (-field(i), i))
+
+
+# ------------------------------------------------- typed keys, per segment
+
+SEG_LENGTHS = [0, 1, 37, 500, 0, 1200, 3, 2, 900]
+
+
+def _seg_offsets(lengths):
+    return np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint64)
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_segments_typed_signed_and_float_match_numpy_per_segment(kb):
+    """Each segment of a typed segmented sort equals numpy's stable argsort of
+    that segment's decoded values (signed integers, finite non-zero floats),
+    ascending and descending; values carry the global input index."""
+    st, ft, ut = ((np.int32, np.float32, np.uint32) if kb == 32
+                  else (np.int64, np.float64, np.uint64))
+    off = _seg_offsets(SEG_LENGTHS)
+    n = int(off[-1])
+    rng = np.random.default_rng(211)
+    v = np.arange(n, dtype=np.uint32)
+    xi = rng.integers(-300, 300, n).astype(st)  # both signs, many ties per segment
+    ints = rng.integers(1, 400, n) * rng.choice([-1, 1], n)
+    xf = (ints * 0.37).astype(ft) * ft(10.0) ** rng.integers(-3, 4, n).astype(ft)
+    for x, key_type in ((xi, oracle.KEY_SIGNED), (xf, oracle.KEY_FLOAT)):
+        for descending in (False, True):
+            ko, vo = oracle.sort_segments(x.view(ut), off, v, key_type=key_type,
+                                          descending=descending)
+            for s in range(len(SEG_LENGTHS)):
+                a, b = int(off[s]), int(off[s + 1])
+                seg = x[a:b].astype(np.float64)  # exact: |x| < 2^53 or already float
+                order = np.argsort(-seg if descending else seg, kind="stable")
+                assert np.array_equal(vo[a:b], a + order), (kb, key_type, descending, s)
+                assert np.array_equal(ko[a:b], x.view(ut)[a:b][order])
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_segments_typed_special_floats_and_bit_ranges_brute_force(kb):
+    """Float special values (NaN payloads, signed zeros, infinities) ranked from
+    decoded values, and descending unsigned sorts of a bit field, per segment,
+    against Python's stable sorted()."""
+    specials = SPECIAL_F32 if kb == 32 else SPECIAL_F64
+    ut = np.uint32 if kb == 32 else np.uint64
+    off = _seg_offsets(SEG_LENGTHS)
+    n = int(off[-1])
+    rng = np.random.default_rng(223)
+    v = np.arange(n, dtype=np.uint32)
+    bits = np.array([specials[i] for i in rng.integers(0, len(specials), n)], dtype=ut)
+    for descending in (False, True):
+        sign = -1 if descending else 1
+        ko, vo = oracle.sort_segments(bits, off, v, key_type=oracle.KEY_FLOAT,
+                                      descending=descending)
+        for s in range(len(SEG_LENGTHS)):
+            a, b = int(off[s]), int(off[s + 1])
+            want = sorted(range(a, b), key=lambda i: (
+                tuple(sign * c for c in _float_class_key(int(bits[i]), kb)), i))
+            assert list(vo[a:b]) == want, (descending, s)
+            assert np.array_equal(ko[a:b], bits[want])
+    k = rng.integers(0, 1 << 20, n, dtype=np.uint64).astype(ut) << ut(kb - 20)
+    k[::5] = k[2]  # ties across and within segments
+    lo, hi = 3, kb - 9
+    fld = lambda i: (int(k[i]) >> lo) & ((1 << (hi - lo)) - 1)  # noqa: E731
+    ko, vo = oracle.sort_segments(k, off, v, lo, hi, descending=True)
+    for s in range(len(SEG_LENGTHS)):
+        a, b = int(off[s]), int(off[s + 1])
+        want = sorted(range(a, b), key=lambda i: (-fld(i), i))
+        assert list(vo[a:b]) == want, s
+        assert np.array_equal(ko[a:b], k[want])
