@@ -182,24 +182,36 @@ def make_keys(dist, n, key_bits, seed=2):
     return W.make_keys(dist, seed, n, key_bits)
 
 
-def cpu_baseline(keys, vals, target_s=10.0):
-    """The CPU oracle, single-threaded, on a bounded sample of the same input."""
-    import numpy as np
+def cpu_model():
+    """CPU model name and the number of logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(keys, vals, max_s=40.0):
+    """The CPU oracle, single-threaded, on the whole input (median of up to
+    three runs, fewer when one run takes longer than max_s / 3)."""
     import oracle
-    sample = min(keys.size, 1 << 26)
-    ks = np.ascontiguousarray(keys[:sample])
-    vs = None if vals is None else np.ascontiguousarray(vals[:sample])
+    model, cpus = cpu_model()
     times = []
-    t_start = time.perf_counter()
-    while len(times) < 3 or (time.perf_counter() - t_start < target_s and len(times) < 10):
+    while len(times) < 3 and sum(times) < max_s:
         t0 = time.perf_counter()
-        oracle.sort(ks, vs)
+        oracle.sort(keys, vals)
         times.append(time.perf_counter() - t0)
     med = statistics.median(times)
-    return {"value": round(sample / med / 1e9, 4), "unit": "GKeys/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first 2^{sample.bit_length() - 1} keys of the same input, "
-                      f"median of {len(times)} single-threaded runs"}
+    n = keys.size
+    return {"value": round(n / med / 1e9, 4), "unit": "GKeys/s", "cores": 1,
+            "kind": "oracle", "cpu": model, "host_cpus": cpus,
+            "sample": f"the whole timed input (2^{n.bit_length() - 1} keys), median of "
+                      f"{len(times)} single-threaded runs of the oracle"}
 
 
 def segment_inputs(num_segments, log2n, seed=4):
@@ -487,21 +499,56 @@ def per_kind_summary(per_kind, ow, lengths, limits, pair_bytes=8):
     return {"table": table, "dominant": (kind, avg_us, launches), "roofline": roof}
 
 
-def is_sorted(out, key_kind, descending, np):
-    """Order check of a sorted output (floating-point keys: the finite values,
-    whose numeric order the sort must follow)."""
-    if key_kind == "float":
-        x = out.view(np.float32 if out.dtype == np.uint32 else np.float64)
-        out = x[np.isfinite(x)]
-    elif key_kind == "signed":
-        out = out.view(np.int32 if out.dtype == np.uint32 else np.int64)
+def ordered_bits_np(keys, key_kind, descending, np):
+    """Raw key bits mapped onto unsigned order (signed: sign bit flipped;
+    floating point: negative values fully complemented, others sign flipped;
+    descending: complemented), a bijection on the bit patterns."""
+    w = keys.dtype.itemsize * 8
+    top = keys.dtype.type(1 << (w - 1))
+    x = keys.copy()
+    if key_kind == "signed":
+        x ^= top
+    elif key_kind == "float":
+        neg = (x & top) != 0
+        x[neg] = ~x[neg]
+        x[~neg] ^= top
     if descending:
-        out = out[::-1]
-    return bool(np.all(out[1:] >= out[:-1]))
+        x = ~x
+    return x
+
+
+def verify_output(keys, vals, d_kout, d_vout, key_kind, descending, np):
+    """Checks the timed sort's output exactly, outside the timed region,
+    with numpy only. Keys only: the stable result of a full-width sort is the
+    sorted multiset, which numpy's sort gives. Pairs (values = input index):
+    keys sorted as numpy sorts them, every value a distinct input index whose
+    key sits at that position, and values increasing within runs of equal
+    keys, which together fix the stable result uniquely. Returns an error
+    message or None."""
+    t0 = time.perf_counter()
+    kout = d_kout.cpu().numpy()
+    want = np.sort(ordered_bits_np(keys, key_kind, descending, np))
+    if not np.array_equal(ordered_bits_np(kout, key_kind, descending, np), want):
+        return "keys differ from the sorted input"
+    del want
+    if vals is not None:
+        vout = d_vout.cpu().numpy()
+        n = keys.size
+        if int(vout.max(initial=0)) >= n:
+            return "a value is not an input index"
+        if np.count_nonzero(np.bincount(vout, minlength=n) != 1):
+            return "values are not a permutation of the input indices"
+        if not np.array_equal(keys[vout], kout):
+            return "a value does not point at its key"
+        tie = kout[1:] == kout[:-1]
+        if np.any(vout[1:][tie] <= vout[:-1][tie]):
+            return "equal keys out of input order (unstable)"
+    log(f"[bench] output verified exactly against numpy ({time.perf_counter() - t0:.1f} s)")
+    return None
 
 
 def rts_baseline(ow, step, places, n, steps, stream, traced_configs, per_kind_times,
-                 plain_config, d_kout, np, key_kind="unsigned", descending=False):
+                 plain_config, check):
     """The reduce-then-scan baseline (Section 2: upsweep, tile scan and
     downsweep per place, ~3pn memory operations against Onesweep's
     ~(2p+1)n) timed on the same input, tile shape and buffers, right after
@@ -530,9 +577,9 @@ def rts_baseline(ow, step, places, n, steps, stream, traced_configs, per_kind_ti
         os_ms.append(timed([plain[ow.ALGORITHM_ONESWEEP]] * k))
         rts_ms.append(timed([plain[ow.ALGORITHM_REDUCE_THEN_SCAN]] * k))
     ms, onesweep_ms = min(rts_ms), min(os_ms)
-    ok = is_sorted(d_kout.cpu().numpy(), key_kind, descending, np)
-    if not ok:
-        log("[bench] ERROR: reduce-then-scan output is not sorted")
+    err = check()
+    if err:
+        log(f"[bench] ERROR: reduce-then-scan output: {err}")
         sys.exit(1)
     cfgs, holders = traced_configs(ow.ALGORITHM_REDUCE_THEN_SCAN, k)
     traced_ms = timed(cfgs)
@@ -689,6 +736,8 @@ def main():
         step(cfg_plain)
     torch.cuda.synchronize()
 
+    # The timed region: `steps` whole sorts back to back, each kernel timed by
+    # events on its own dispatch packet (no extra work on the stream).
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
@@ -702,6 +751,16 @@ def main():
     ms_per_step = ms_total / steps
     value = n / (ms_per_step * 1e-3) / 1e9
     log(f"[bench] {steps} steps in {ms_total:.3f} ms (wall {wall * 1e3:.1f} ms)")
+    # The same steps without per-kernel timing, for comparison.
+    u0, u1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    u0.record(stream)
+    for k in range(steps):
+        step(cfg_plain)
+    u1.record(stream)
+    torch.cuda.synchronize()
+    untraced_ms = u0.elapsed_time(u1) / steps
+    log(f"[bench] untimed kernels: {untraced_ms:.4f} ms per step "
+        f"(timed: {ms_per_step:.4f} ms)")
 
     # Per-step durations (first launch's start to last launch's end of each
     # step, from the traced events): median, min and interquartile range.
@@ -719,10 +778,10 @@ def main():
         log(f"[bench]   {ow.KERNEL_NAMES[kind]:9s} launches={len(ts):4d} "
             f"avg={statistics.mean(ts) * 1e3:9.2f} us  total/step={sum(ts) / steps * 1e3:9.2f} us")
 
-    # Correctness spot check of the timed result (full check lives in tests/).
-    sorted_ok = is_sorted(d_kout.cpu().numpy(), key_kind, descending, np)
-    if not sorted_ok:
-        log("[bench] ERROR: output is not sorted")
+    # Exact check of the timed result (every step wrote the same output).
+    err = verify_output(keys, vals, d_kout, d_vout, key_kind, descending, np)
+    if err:
+        log(f"[bench] ERROR: {err}")
         sys.exit(1)
 
     kb = key_bits // 8
@@ -787,6 +846,8 @@ def main():
             "copy_kernel_gbs": round(copy_gbs, 1),
             "whole_sort_over_copy": round(whole_gbs / copy_gbs, 4),
             "per_step": step_stats,
+            "untimed_kernels_ms_per_step": round(untraced_ms, 4),
+            "output_verified": "exact, against numpy's sort of the input",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -805,11 +866,11 @@ def main():
             return ow.make_config(args.block, args.ipt, args.hist_blocks_per_cu,
                                   rank_algorithm=args.rank, algorithm=alg,
                                   key_type=key_type, descending=descending)
-        result["reduce_then_scan"] = rts_baseline(ow, step, places, n, steps, stream,
-                                                  traced_configs, per_kind_times, plain_config,
-                                                  d_kout, np, key_kind, descending)
+        result["reduce_then_scan"] = rts_baseline(
+            ow, step, places, n, steps, stream, traced_configs, per_kind_times, plain_config,
+            lambda: verify_output(keys, vals, d_kout, d_vout, key_kind, descending, np))
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
+        log("[bench] timing the CPU oracle on the whole input")
         result["cpu_baseline"] = cpu_baseline(keys, vals)
     print(json.dumps(result), flush=True)
 

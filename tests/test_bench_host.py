@@ -58,3 +58,51 @@ def test_counter_summary_scales_by_the_copy_and_keeps_chained_binning_only(tmp_p
     # read back only for its own workload and the current kernel sources
     assert abs(bench.read_traffic("u32_keys_uniform") - want) < 2
     assert bench.read_traffic("u32_pairs_uniform") is None
+
+
+class _Host:
+    """Stands in for a device tensor: .cpu().numpy() returns the array."""
+
+    def __init__(self, a):
+        self.a = a
+
+    def cpu(self):
+        return self
+
+    def numpy(self):
+        return self.a
+
+
+def test_output_verification_accepts_the_stable_sort_and_rejects_wrong_ones():
+    import numpy as np
+    bench = load_bench()
+    rng = np.random.default_rng(5)
+    keys = rng.integers(0, 50, 5000).astype(np.uint32)  # many ties
+    vals = np.arange(keys.size, dtype=np.uint32)
+    order = np.argsort(keys, kind="stable").astype(np.uint32)
+    ko, vo = keys[order], order
+    check = lambda k, v, kind="unsigned", desc=False: bench.verify_output(  # noqa: E731
+        keys, vals, _Host(k), None if v is None else _Host(v), kind, desc, np)
+    assert check(ko, vo) is None
+    assert bench.verify_output(keys, None, _Host(ko), None, "unsigned", False, np) is None
+    # same byte histograms, sum, XOR and order as a sorted {0x0101, 0x0202}, yet wrong
+    two = np.array([0x0101, 0x0202], dtype=np.uint32)
+    bad = np.array([0x0102, 0x0201], dtype=np.uint32)
+    assert bench.verify_output(two, None, _Host(bad), None, "unsigned", False, np)
+    unstable = vo.copy()
+    i = int(np.flatnonzero(ko[1:] == ko[:-1])[0])
+    unstable[i], unstable[i + 1] = unstable[i + 1], unstable[i]
+    assert "unstable" in check(ko, unstable)
+    wrong = vo.copy()
+    wrong[0], wrong[-1] = wrong[-1], wrong[0]
+    assert check(ko, wrong)
+    dup = vo.copy()
+    dup[1] = dup[0]
+    assert "permutation" in check(ko, dup)
+    # signed and descending orders
+    s = rng.integers(-100, 100, 3000).astype(np.int32)
+    want = np.sort(s)[::-1].copy()
+    assert bench.verify_output(s.view(np.uint32), None, _Host(want.view(np.uint32)), None,
+                               "signed", True, np) is None
+    assert bench.verify_output(s.view(np.uint32), None, _Host(np.sort(s).view(np.uint32)), None,
+                               "signed", True, np)
