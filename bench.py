@@ -214,6 +214,30 @@ def cpu_baseline(keys, vals, max_s=40.0):
                       f"{len(times)} single-threaded runs of the oracle"}
 
 
+def cpu_parallel_baseline(keys, vals, max_s=30.0):
+    """A multithreaded LSD radix sort (OpenMP, every core this process may
+    use) on the whole input: the secondary CPU baseline, checked against the
+    oracle in tests/test_cpu_baseline.py. Median of up to three runs."""
+    import numpy as np
+    import cpu_baseline
+    model, cpus = cpu_model()
+    threads = cpu_baseline.threads_used()
+    times = []
+    while len(times) < 3 and sum(times) < max_s:
+        t0 = time.perf_counter()
+        k, _ = cpu_baseline.sort(keys, vals)
+        times.append(time.perf_counter() - t0)
+    if keys.dtype == np.uint32 and vals is None and not np.array_equal(k, np.sort(keys)):
+        log("[bench] ERROR: the multithreaded CPU sort differs from numpy's sort")
+        sys.exit(1)
+    med = statistics.median(times)
+    n = keys.size
+    return {"value": round(n / med / 1e9, 4), "unit": "GKeys/s", "cores": threads,
+            "kind": "multithreaded LSD radix sort (OpenMP)", "cpu": model, "host_cpus": cpus,
+            "sample": f"the whole timed input (2^{n.bit_length() - 1} keys), median of "
+                      f"{len(times)} runs on {threads} threads"}
+
+
 def segment_inputs(num_segments, log2n, seed=4):
     import numpy as np
     import workload as W
@@ -247,15 +271,17 @@ def cpu_baseline_segments(keys, vals, off, target_s=10.0):
                       f"{len(times)} single-threaded runs"}
 
 
-def run_segments(args):
-    """Batched segmented sort under a captured graph, against per-segment
-    loops of the plain pair sort (eager, and captured in one graph)."""
+def segments_leg(args, S, log2n, tune=False, with_loops=True):
+    """The batched segmented sort, one captured graph replayed `steps` times
+    (configuration: the command line's, or the autotuner's pick on this data
+    when `tune`), its output spot-checked, per-kernel durations from eager
+    traced runs, and the per-segment loops of plain pair sorts as baselines.
+    Returns a dict of the measurements."""
     import numpy as np
     import torch
     import paper_2206_01784_amd as ow
 
-    S, log2n = SEGMENT_WORKLOADS[args.workload]
-    log(f"[bench] workload={args.workload} generating input")
+    log(f"[bench] segments: {S} log-normal segments, 2^{log2n} pairs, generating input")
     lengths, off, keys, vals = segment_inputs(S, log2n)
     n = int(off[-1])
     stream = torch.cuda.current_stream()
@@ -264,8 +290,18 @@ def run_segments(args):
     d_off = torch.from_numpy(off.astype(np.uint32)).cuda()
     d_kout = torch.empty_like(d_keys)
     d_vout = torch.empty_like(d_vals)
-    cfg = ow.make_config(args.block, args.ipt, rank_algorithm=args.rank,
-                         segment_limits=tuple(args.segment_limits),
+    if tune:
+        t0 = time.perf_counter()
+        tuned = ow.tune_segments(d_keys, d_off, d_vals, keys_out=d_kout, values_out=d_vout,
+                                 repetitions=3)
+        torch.cuda.synchronize()
+        block, ipt = tuned.block_threads, tuned.items_per_thread
+        limits = tuple(tuned.segment_limits)
+        log(f"[bench] segments: autotuner picked tile {block} x {ipt}, class limits {limits} "
+            f"({time.perf_counter() - t0:.1f} s)")
+    else:
+        block, ipt, limits = args.block, args.ipt, tuple(args.segment_limits)
+    cfg = ow.make_config(block, ipt, rank_algorithm=args.rank, segment_limits=limits,
                          segment_streams=args.segment_streams)
     temp = torch.empty(ow.sort_segments_temp_bytes(n, S, 32, True, config=cfg),
                        dtype=torch.uint8, device="cuda")
@@ -288,8 +324,8 @@ def run_segments(args):
         tr = ow.Trace()
         tr.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
         tr.capacity = launches
-        cfg_t = ow.make_config(args.block, args.ipt, rank_algorithm=args.rank,
-                               segment_limits=tuple(args.segment_limits), trace=tr)
+        cfg_t = ow.make_config(block, ipt, rank_algorithm=args.rank, segment_limits=limits,
+                               trace=tr)
         batched(cfg_t)
         torch.cuda.synchronize()
         for i in range(tr.count):
@@ -333,21 +369,35 @@ def run_segments(args):
         if not ok:
             log(f"[bench] ERROR: segment {s_} is not a stable sort of its input")
             sys.exit(1)
-
     baselines = None
-    if not args.no_loop_baseline:
-        baselines = loop_baselines(args, ow, off, lengths, n, S, d_keys, d_vals, d_kout, d_vout,
-                                   stream, cap, ms_per_step)
-    bins = per_kind_summary(per_kind, ow, lengths, args.segment_limits)
+    if with_loops:
+        baselines = loop_baselines(ow, off, n, S, d_keys, d_vals, d_kout, d_vout, stream, cap,
+                                   ms_per_step)
+    return {"n": n, "lengths": lengths, "off": off, "keys": keys, "vals": vals,
+            "ms_per_step": ms_per_step, "value": value, "block": block, "ipt": ipt,
+            "limits": limits, "tuned": tune, "tile": ow.tile_items(32, True, cfg, n),
+            "per_kind": per_kind, "baselines": baselines}
+
+
+def run_segments(args):
+    """Batched segmented sort under a captured graph, against per-segment
+    loops of the plain pair sort (eager, and captured in graphs)."""
+    import paper_2206_01784_amd as ow
+
+    S, log2n = SEGMENT_WORKLOADS[args.workload]
+    leg = segments_leg(args, S, log2n, tune=args.tune_segments,
+                       with_loops=not args.no_loop_baseline)
+    n, lengths = leg["n"], leg["lengths"]
+    bins = per_kind_summary(leg["per_kind"], ow, lengths, leg["limits"])
     dom_kind, dom_us, dom_launches = bins["dominant"]
     result = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(leg["value"], 3),
         "unit": "GKeys/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(leg["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -357,85 +407,86 @@ def run_segments(args):
             "workload": f"batched stable sort of {S} segments (log-normal lengths, median 2000, "
                         f"sigma 1.5, scaled to 2^{log2n} uint32 key/value pairs), one graph replay",
             "n": n, "segments": S, "key_bits": 32, "values": True,
-            "segment_limits": list(args.segment_limits),
+            "segment_limits": list(leg["limits"]),
             "segment_streams": 1 if args.segment_streams == 1 else 2,
-            "tile": ow.tile_items(32, True, cfg, n),
+            "tile": leg["tile"],
+            "autotuned": leg["tuned"],
         },
-        "baselines": baselines,
+        "baselines": leg["baselines"],
         "kernels_us": bins["table"],
         "roofline": bins["roofline"] if dom_kind is not None else None,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline_segments(keys, vals, off)
+        result["cpu_baseline"] = cpu_baseline_segments(leg["keys"], leg["vals"], leg["off"])
     print(json.dumps(result), flush=True)
 
 
-def loop_baselines(args, ow, off, lengths, n, S, d_keys, d_vals, d_kout, d_vout, stream, cap,
-                   ms_per_step):
-    """The per-segment loop of plain pair sorts, eager and graph-captured."""
+def loop_baselines(ow, off, n, S, d_keys, d_vals, d_kout, d_vout, stream, cap, ms_per_step):
+    """The per-segment loop of plain pair sorts over every segment: eager, and
+    captured in graphs of LOOP_GRAPH_SEGMENTS segments each (all of them
+    replayed back to back). One graph holding the whole loop (about 8 launches
+    per segment, ~160,000 kernel nodes) ended the process with a segmentation
+    fault on the host during capture; graphs of 500 segments (~4,000 nodes)
+    capture and replay normally, so the loop is cut into such graphs."""
     import torch
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # Baseline 1: a loop of plain pair sorts, one per segment, eager.
+    lengths = off[1:] - off[:-1]
     seg_temp = torch.empty(ow.sort_temp_bytes(int(lengths.max()), 32, True), dtype=torch.uint8,
                            device="cuda")
     bounds = [(int(off[i]), int(off[i + 1])) for i in range(S) if off[i + 1] > off[i]]
 
-    def loop(s=stream):
-        for a, b in bounds:
+    def loop(segs, s):
+        for a, b in segs:
             ow.sort_pairs(d_keys[a:b], d_vals[a:b], keys_out=d_kout[a:b], values_out=d_vout[a:b],
                           temp=seg_temp, stream=s)
 
-    loop()
+    # Baseline 1: eager loop.
+    loop(bounds, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
-    loop()
-    end.record()
+    start.record(stream)
+    loop(bounds, stream)
+    end.record(stream)
     torch.cuda.synchronize()
     loop_ms = (time.perf_counter() - t0) * 1e3
     loop_gpu_ms = start.elapsed_time(end)
     log(f"[bench] per-segment loop (eager): {loop_ms:.1f} ms wall, {loop_gpu_ms:.1f} ms on the stream")
-    # Baseline 2: the loop captured into one graph, on a bounded sample (the
-    # first LOOP_GRAPH_SEGMENTS non-empty segments, 8 launches each), scaled
-    # to all segments by their key count.
-    sample = bounds[:LOOP_GRAPH_SEGMENTS]
-    sample_keys = sum(b - a for a, b in sample)
-
-    def loop_sample(s):
-        for a, b in sample:
-            ow.sort_pairs(d_keys[a:b], d_vals[a:b], keys_out=d_kout[a:b], values_out=d_vout[a:b],
-                          temp=seg_temp, stream=s)
-
-    start.record()
-    loop_sample(stream)
-    end.record()
+    # Baseline 2: the same loop as consecutive graphs of LOOP_GRAPH_SEGMENTS
+    # segments each, every graph replayed once per timed run.
+    chunks = [bounds[i:i + LOOP_GRAPH_SEGMENTS] for i in range(0, len(bounds), LOOP_GRAPH_SEGMENTS)]
+    graphs = []
+    t0 = time.perf_counter()
+    for ch in chunks:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(g, stream=cap):
+                loop(ch, cap)
+        graphs.append(g)
     torch.cuda.synchronize()
-    sample_eager_ms = start.elapsed_time(end)
-    g2 = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(cap):
-        with torch.cuda.graph(g2, stream=cap):
-            loop_sample(cap)
+    log(f"[bench] per-segment loop captured as {len(graphs)} graphs of up to "
+        f"{LOOP_GRAPH_SEGMENTS} segments ({time.perf_counter() - t0:.1f} s)")
+    for g in graphs:
+        g.replay()
     torch.cuda.synchronize()
-    g2.replay()
-    torch.cuda.synchronize()
-    start.record()
-    g2.replay()
-    end.record()
-    torch.cuda.synchronize()
-    sample_graph_ms = start.elapsed_time(end)
-    loop_graph_ms = sample_graph_ms * n / sample_keys
-    log(f"[bench] per-segment loop on the first {len(sample)} segments ({sample_keys} pairs): "
-        f"eager {sample_eager_ms:.2f} ms, graph {sample_graph_ms:.2f} ms; graph scaled to all "
-        f"keys {loop_graph_ms:.1f} ms")
-    del g2
+    runs = []
+    for _ in range(3):
+        start.record()
+        for g in graphs:
+            g.replay()
+        end.record()
+        torch.cuda.synchronize()
+        runs.append(start.elapsed_time(end))
+    loop_graph_ms = statistics.median(runs)
+    log(f"[bench] per-segment loop (graphs): {loop_graph_ms:.1f} ms (runs {runs})")
+    del graphs
     return {
         "per_segment_loop_ms": round(loop_gpu_ms, 2),
         "per_segment_loop_wall_ms": round(loop_ms, 2),
-        "per_segment_loop_graph_ms_scaled": round(loop_graph_ms, 2),
-        "per_segment_loop_graph_sample": f"first {len(sample)} segments, {sample_keys} pairs, "
-                                         f"{sample_graph_ms:.2f} ms",
+        "per_segment_loop_graph_ms": round(loop_graph_ms, 2),
+        "per_segment_loop_graph_chunks": f"{len(chunks)} graphs of up to {LOOP_GRAPH_SEGMENTS} "
+                                         f"segments, {len(bounds)} segments in all",
         "speedup_vs_loop": round(loop_gpu_ms / ms_per_step, 1),
         "speedup_vs_loop_graph": round(loop_graph_ms / ms_per_step, 1),
     }
@@ -614,6 +665,11 @@ def main():
                     help="segmented workload: 0 two streams (default), 1 one stream")
     ap.add_argument("--no-loop-baseline", action="store_true",
                     help="segmented workload: skip the per-segment loop baselines")
+    ap.add_argument("--no-segments", action="store_true",
+                    help="default workload: skip the batched segmented sort beside it")
+    ap.add_argument("--tune-segments", action="store_true",
+                    help="segmented workload: time the configuration the autotuner picks on "
+                         "this data instead of the command line's")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--hist-blocks-per-cu", type=int, default=0)
@@ -736,14 +792,14 @@ def main():
         step(cfg_plain)
     torch.cuda.synchronize()
 
-    # The timed region: `steps` whole sorts back to back, each kernel timed by
-    # events on its own dispatch packet (no extra work on the stream).
+    # The timed region: `steps` whole sorts back to back, with events only at
+    # its two ends (nothing else on the stream).
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     start.record(stream)
     for k in range(steps):
-        step(cfgs[k])
+        step(cfg_plain)
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -751,26 +807,28 @@ def main():
     ms_per_step = ms_total / steps
     value = n / (ms_per_step * 1e-3) / 1e9
     log(f"[bench] {steps} steps in {ms_total:.3f} ms (wall {wall * 1e3:.1f} ms)")
-    # The same steps without per-kernel timing, for comparison.
-    u0, u1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    u0.record(stream)
+    # The same steps again with HIP events around every launch, on the stream
+    # the kernels run on: per-kernel durations and per-step spreads. The
+    # events are packets of their own between the kernels, so these steps
+    # run slightly longer than the timed ones.
+    t0_, t1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0_.record(stream)
     for k in range(steps):
-        step(cfg_plain)
-    u1.record(stream)
+        step(cfgs[k])
+    t1_.record(stream)
     torch.cuda.synchronize()
-    untraced_ms = u0.elapsed_time(u1) / steps
-    log(f"[bench] untimed kernels: {untraced_ms:.4f} ms per step "
-        f"(timed: {ms_per_step:.4f} ms)")
+    traced_ms = t0_.elapsed_time(t1_) / steps
+    log(f"[bench] traced steps: {traced_ms:.4f} ms per step (timed, untraced: {ms_per_step:.4f} ms)")
 
     # Per-step durations (first launch's start to last launch's end of each
-    # step, from the traced events): median, min and interquartile range.
+    # traced step): median, min and interquartile range.
     step_ms = sorted(evs[0].elapsed_time(evs[2 * tr.count - 1]) for tr, evs, _ in holders
                      if tr.count > 0)
     q = lambda f: step_ms[min(len(step_ms) - 1, int(f * (len(step_ms) - 1) + 0.5))]  # noqa: E731
     step_stats = {"median_ms": round(q(0.5), 4), "min_ms": round(step_ms[0], 4),
                   "iqr_ms": round(q(0.75) - q(0.25), 4)}
-    log(f"[bench] per step: median {step_stats['median_ms']} ms, min {step_stats['min_ms']} ms, "
-        f"IQR {step_stats['iqr_ms']} ms")
+    log(f"[bench] per traced step: median {step_stats['median_ms']} ms, min "
+        f"{step_stats['min_ms']} ms, IQR {step_stats['iqr_ms']} ms")
 
     # Per-kernel durations from the traced events.
     per_kind = per_kind_times(holders)
@@ -845,8 +903,8 @@ def main():
             "hbm_fraction_whole_sort": round(whole_gbs / HBM_PEAK_GBS, 4),
             "copy_kernel_gbs": round(copy_gbs, 1),
             "whole_sort_over_copy": round(whole_gbs / copy_gbs, 4),
-            "per_step": step_stats,
-            "untimed_kernels_ms_per_step": round(untraced_ms, 4),
+            "per_traced_step": step_stats,
+            "traced_ms_per_step": round(traced_ms, 4),
             "output_verified": "exact, against numpy's sort of the input",
         },
         "roofline": {
@@ -869,9 +927,32 @@ def main():
         result["reduce_then_scan"] = rts_baseline(
             ow, step, places, n, steps, stream, traced_configs, per_kind_times, plain_config,
             lambda: verify_output(keys, vals, d_kout, d_vout, key_kind, descending, np))
+    if not args.no_segments and args.workload == "u32_keys_uniform":
+        # The batched form beside the plain sort: the segmented workload in
+        # the configuration the autotuner picks on it, against the
+        # per-segment loop of plain pair sorts.
+        S, log2n_s = SEGMENT_WORKLOADS["segments_lognormal_20000"]
+        leg = segments_leg(args, S, log2n_s, tune=True, with_loops=True)
+        b = leg["baselines"]
+        result["segments"] = {
+            "workload": f"batched stable sort of {S} segments (log-normal lengths, median 2000, "
+                        f"sigma 1.5, scaled to 2^{log2n_s} uint32 key/value pairs), one graph "
+                        "replay per step",
+            "n": leg["n"], "ms_per_step": round(leg["ms_per_step"], 4),
+            "value": round(leg["value"], 3), "unit": "GKeys/s",
+            "tile": f"{leg['block']}x{leg['ipt']}", "segment_limits": list(leg["limits"]),
+            "autotuned": True,
+            "per_segment_loop_ms": b["per_segment_loop_ms"],
+            "per_segment_loop_graph_ms": b["per_segment_loop_graph_ms"],
+            "speedup_vs_loop": b["speedup_vs_loop"],
+            "speedup_vs_loop_graph": b["speedup_vs_loop_graph"],
+        }
+        del leg
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on the whole input")
         result["cpu_baseline"] = cpu_baseline(keys, vals)
+        log("[bench] timing the multithreaded CPU sort on the whole input")
+        result["cpu_parallel_baseline"] = cpu_parallel_baseline(keys, vals)
     print(json.dumps(result), flush=True)
 
 

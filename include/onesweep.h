@@ -265,7 +265,9 @@ onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
 /*
  * Autotuner of the segmented sort (not in the paper): times
  * onesweep_sort_segments on the caller's data for every built tile shape of
- * the segmented path crossed with a fixed set of segment class limits
+ * the segmented path (32-bit keys: 256x8, 256x16, 512x16, 1024x8, 1024x11;
+ * 64-bit keys: 256x8, 256x16, 512x8, 1024x8, 1024x9) crossed with seven
+ * settings of the segment class limits
  * (`repetitions` timed runs each, after one warm-up), writes the fastest
  * configuration to *cfg_out and leaves the output sorted by it. Arguments as
  * in onesweep_sort_segments, except that input and output must not alias

@@ -967,11 +967,13 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
   // Candidates: every tile shape built for the segmented path, crossed with
   // class limits that move segments between the LDS classes and the tile
   // path.
-  static const int kShapes32[][2] = {{256, 16}, {512, 16}, {1024, 8}};
-  static const int kShapes64[][2] = {{256, 16}, {512, 8}, {1024, 8}};
+  static const int kShapes32[][2] = {{256, 8}, {256, 16}, {512, 16}, {1024, 8}, {1024, 11}};
+  static const int kShapes64[][2] = {{256, 8}, {256, 16}, {512, 8}, {1024, 8}, {1024, 9}};
   static const int kLimits[][3] = {{0, 0, 0},   {0, 0, 4096},  {0, 0, 2048}, {0, 0, -1},
                                    {0, -1, 0},  {-1, 0, 0},    {256, 1024, 4096}};
-  constexpr int kNumShapes = 3, kNumLimits = sizeof(kLimits) / sizeof(kLimits[0]);
+  constexpr int kNumShapes = sizeof(kShapes32) / sizeof(kShapes32[0]);
+  constexpr int kNumLimits = sizeof(kLimits) / sizeof(kLimits[0]);
+  static_assert(sizeof(kShapes64) == sizeof(kShapes32), "one shape list per key width");
   // The key order comes in through *cfg_out and is kept by every candidate.
   const int key_type = cfg_out ? cfg_out->key_type : ONESWEEP_KEY_UNSIGNED;
   const int descending = cfg_out ? cfg_out->descending : 0;
