@@ -189,6 +189,34 @@ onesweep_status_t onesweep_sort_pairs(void *d_temp, size_t *temp_bytes, const vo
                                       const onesweep_config_t *cfg, onesweep_stream_t stream);
 
 /*
+ * Allocation-free keys-only sort, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops and harnesses
+ * that forbid hipMalloc. Same arguments, semantics and output as
+ * onesweep_sort_keys, without d_temp / temp_bytes: the temporary storage is
+ * a library-owned device array of ONESWEEP_NOALLOC_SCRATCH_BYTES (64 MiB) on
+ * each GPU the library runs on, held until the process ends. The call
+ * allocates nothing; it enqueues kernels only (graph-capturable).
+ *  - Size limit: the temporary storage onesweep_sort_keys would need (its
+ *    size query, which depends on n, key_bits, the bit range and cfg) must
+ *    fit the array; with the default configuration that is about 15.4
+ *    million 32-bit or 7.5 million 64-bit keys. Larger inputs return
+ *    ONESWEEP_ERROR_TOO_LARGE before anything is enqueued.
+ *  - The first call on a device looks up the array's device address
+ *    (hipGetSymbolAddress, which may load the library's code on that
+ *    device); make that call outside graph capture.
+ *  - Every call on one GPU uses the same array: calls that overlap on one
+ *    GPU (concurrent streams, threads or processes sharing the library
+ *    instance) race and give wrong results; serialise them. Each call clears
+ *    what must start at zero, so the previous call's contents do not matter.
+ * Other errors as in onesweep_sort_keys.
+ */
+#define ONESWEEP_NOALLOC_SCRATCH_BYTES (64u << 20)
+onesweep_status_t onesweep_sort_keys_noalloc(const void *d_keys_in, void *d_keys_out, size_t n,
+                                             int key_bits, int begin_bit, int end_bit,
+                                             int stable, const onesweep_config_t *cfg,
+                                             onesweep_stream_t stream);
+
+/*
  * Phase 1 alone (Section 3, upfront histogram kernel): d_hist[j * 256 + v]
  * receives the number of keys whose digit at place j is v (digits of the
  * key bits as cfg's key_type and descending order them), for all

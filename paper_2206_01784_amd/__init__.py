@@ -58,6 +58,7 @@ _szp = ctypes.POINTER(ctypes.c_size_t)
 _cfgp = ctypes.POINTER(Config)
 
 _lib.onesweep_sort_keys.argtypes = [_vp, _szp, _vp, _vp, _sz, _i32, _i32, _i32, _i32, _cfgp, _vp]
+_lib.onesweep_sort_keys_noalloc.argtypes = [_vp, _vp, _sz, _i32, _i32, _i32, _i32, _cfgp, _vp]
 _lib.onesweep_sort_pairs.argtypes = [_vp, _szp, _vp, _vp, _vp, _vp, _sz, _i32, _i32, _i32, _i32,
                                      _cfgp, _vp]
 _lib.onesweep_histogram.argtypes = [_vp, _sz, _i32, _i32, _i32, _vp, _cfgp, _vp]
@@ -72,7 +73,8 @@ _lib.onesweep_tile_items.argtypes = [_i32, _i32, _sz, _cfgp]
 _lib.onesweep_tile_items.restype = _sz
 _lib.onesweep_last_error.restype = ctypes.c_char_p
 _lib.onesweep_version.restype = ctypes.c_char_p
-for _f in ("onesweep_sort_keys", "onesweep_sort_pairs", "onesweep_histogram",
+NOALLOC_SCRATCH_BYTES = 64 << 20
+for _f in ("onesweep_sort_keys", "onesweep_sort_keys_noalloc", "onesweep_sort_pairs", "onesweep_histogram",
            "onesweep_binning_pass", "onesweep_sort_segments"):
     getattr(_lib, _f).restype = _i32
 
@@ -212,6 +214,24 @@ def sort_keys(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None
     _check(_lib.onesweep_sort_keys(_dev_ptr(temp), ctypes.byref(size), _dev_ptr(keys),
                                    _dev_ptr(out), n, kb, begin_bit, end_bit, 1,
                                    _cfg_ptr(config), _stream(stream)))
+    return out
+
+
+def sort_keys_noalloc(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
+                      out: torch.Tensor | None = None, config: Config | None = None, stream=None,
+                      descending: bool = False) -> torch.Tensor:
+    """sort_keys through the allocation-free entry point: the library's own
+    64 MiB device array per GPU serves as temporary storage, so the C call
+    allocates nothing (pass `out` to avoid torch's allocation too). Calls
+    that overlap on one GPU race."""
+    kb = _key_bits(keys)
+    config = _ordered_config(config, keys, descending)
+    end_bit = kb if end_bit is None else end_bit
+    if out is None:
+        out = torch.empty_like(keys)
+    _check(_lib.onesweep_sort_keys_noalloc(_dev_ptr(keys), _dev_ptr(out), keys.numel(), kb,
+                                           begin_bit, end_bit, 1, _cfg_ptr(config),
+                                           _stream(stream)))
     return out
 
 

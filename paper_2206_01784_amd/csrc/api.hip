@@ -795,12 +795,75 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   return ONESWEEP_SUCCESS;
 }
 
+// ------------------------------------------------ allocation-free keys sort
+
+// Temporary storage of onesweep_sort_keys_noalloc: one array per GPU, loaded
+// with the library's code object and kept until the process ends. Host code
+// never uses the array's name as an address (in host code it is only a
+// stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, resolved once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(ONESWEEP_NOALLOC_SCRATCH_BYTES);
+static_assert(kNoAllocScratchBytes % kAlign == 0, "scratch is a whole number of 256-byte slots");
+
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[64];  // per device id, guarded by g_scratch_mutex
+
+}  // namespace
+}  // namespace onesweep
+
+static __device__ __align__(256) unsigned char scratch[onesweep::kNoAllocScratchBytes];
+
+namespace onesweep {
+namespace {
+
+// Device address of the current device's scratch array.
+onesweep_status_t scratch_address(void **ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(ONESWEEP_ERROR_UNSUPPORTED, "device id %d not below 64", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (p == nullptr || (reinterpret_cast<uintptr_t>(p) & (kAlign - 1)) != 0)
+      return fail(ONESWEEP_ERROR_HIP, "scratch array address %p is not 256-byte aligned", p);
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return ONESWEEP_SUCCESS;
+}
+
 }  // namespace
 }  // namespace onesweep
 
 using namespace onesweep;
 
 extern "C" {
+
+onesweep_status_t onesweep_sort_keys_noalloc(const void *d_keys_in, void *d_keys_out, size_t n,
+                                             int key_bits, int begin_bit, int end_bit,
+                                             int stable, const onesweep_config_t *cfg,
+                                             onesweep_stream_t stream) {
+  (void)stable;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  size_t need = 0;
+  onesweep_status_t st = sort_impl(nullptr, &need, d_keys_in, d_keys_out, nullptr, nullptr, false,
+                                   n, key_bits, begin_bit, end_bit, cfg, s);
+  if (st) return st;
+  if (need > kNoAllocScratchBytes)
+    return fail(ONESWEEP_ERROR_TOO_LARGE,
+                "n = %zu %d-bit keys need %zu bytes of temporary storage; the allocation-free "
+                "sort has %zu (use onesweep_sort_keys)",
+                n, key_bits, need, kNoAllocScratchBytes);
+  if (n == 0) return ONESWEEP_SUCCESS;
+  void *temp = nullptr;
+  if ((st = scratch_address(&temp))) return st;
+  size_t have = kNoAllocScratchBytes;
+  return sort_impl(temp, &have, d_keys_in, d_keys_out, nullptr, nullptr, false, n, key_bits,
+                   begin_bit, end_bit, cfg, s);
+}
 
 onesweep_status_t onesweep_sort_keys(void *d_temp, size_t *temp_bytes, const void *d_keys_in,
                                      void *d_keys_out, size_t n, int key_bits, int begin_bit,
