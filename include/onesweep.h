@@ -36,8 +36,15 @@
  *  - The chained-scan status words hold 30-bit values (Section 3, "Handling
  *    very large problems"): one chained scan covers fewer than 2^30 keys.
  *    Whole plain sorts (onesweep_sort_keys/pairs) bin large inputs in strips
- *    of at most 2^29 keys and accept n below 2^31; the other entry points
- *    accept n below 2^30. Larger n returns ONESWEEP_ERROR_TOO_LARGE.
+ *    of at most 2^29 keys, each its own chained scan whose last tile hands
+ *    the next strip its bin starts. From 2^31 elements on they also keep
+ *    64-bit histogram counts (the upfront histogram runs over portions of at
+ *    most 2^30 keys), 64-bit bin starts and 64-bit element positions, as
+ *    that section describes, and accept n below 2^36; at those sizes only
+ *    the default tile shape of each key width and value presence is built
+ *    (other tile configurations return ONESWEEP_ERROR_UNSUPPORTED) and the
+ *    reduce-then-scan baseline is not. The other entry points accept n
+ *    below 2^30. Larger n returns ONESWEEP_ERROR_TOO_LARGE.
  *  - Errors are returned as status codes; nothing is enqueued when argument
  *    validation fails. onesweep_last_error() describes the last failure of
  *    the calling thread.
@@ -57,7 +64,7 @@ typedef struct ihipStream_t *onesweep_stream_t; /* same type as hipStream_t */
 typedef enum {
     ONESWEEP_SUCCESS = 0,
     ONESWEEP_ERROR_INVALID_VALUE = 1,     /* bad pointer, width, bit range, overlap */
-    ONESWEEP_ERROR_TOO_LARGE = 2,         /* n beyond the entry point's limit (2^31 or 2^30) */
+    ONESWEEP_ERROR_TOO_LARGE = 2,         /* n beyond the entry point's limit (2^36 or 2^30) */
     ONESWEEP_ERROR_INSUFFICIENT_TEMP = 3, /* *temp_bytes below the required size */
     ONESWEEP_ERROR_HIP = 4,               /* a HIP runtime call failed */
     ONESWEEP_ERROR_UNSUPPORTED = 5        /* configuration not built into the library */
@@ -164,6 +171,19 @@ typedef struct {
                                 bin starts (Section 3, handling very large problems).
                                 0 = 29, the default; else 11..29. Smaller strips only
                                 serve tests of inputs below 2^29. */
+    int lookback_spin_limit; /* bound of the look-back wait (Section 3: a tile
+                                walks back over its predecessors' status words,
+                                waiting on N, until it meets an inclusive prefix):
+                                after this many polls of its window of
+                                predecessors without meeting one, the tile gives
+                                up, records a look-back error in temporary storage
+                                and carries on with a wrong sum, so a protocol fault
+                                ends the kernel (with wrong output) instead of
+                                hanging the GPU. 0 = 2^22 polls (seconds; a
+                                legitimate look-back takes a few). Where the error
+                                is recorded: onesweep_binning_pass documents it; for
+                                the other entry points it is internal. Negative
+                                values are invalid. */
     onesweep_trace_t *trace; /* optional launch timing, may be NULL */
 } onesweep_config_t;
 
@@ -236,10 +256,12 @@ onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits,
  * the exclusive sum of the digit counts. 1 <= width <= 8,
  * shift + width <= key_bits. src and dst must not overlap.
  * Temp layout (documented so tests can read the chained-scan state): bytes
- * [0, 256) hold the tile counter, then ceil(n / T) rows of 256 uint32 status
- * words (row = tile, column = digit; Figure 6 layout: 2-bit status above a
- * 30-bit value). After the pass every word holds status G (2) and the tile's
- * inclusive prefix count.
+ * [0, 256) hold the tile counter (uint32 0) and the look-back error word
+ * (uint32 1: 0, or 1 when a tile gave up waiting, see
+ * onesweep_config_t.lookback_spin_limit), then ceil(n / T) rows of 256 uint32
+ * status words (row = tile, column = digit; Figure 6 layout: 2-bit status
+ * above a 30-bit value). After a pass without look-back error every word
+ * holds status G (2) and the tile's inclusive prefix count.
  */
 onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
                                         const void *d_src_keys, void *d_dst_keys,
@@ -402,7 +424,9 @@ onesweep_status_t onesweep_model_train_step(onesweep_model_t *model, const float
                                             const float *d_mask, int batch, float lr,
                                             float *d_loss, onesweep_stream_t stream);
 /* Configuration for sorting these keys: features and one forward pass in a
- * single kernel, the best class that applies to key_bits, then a
+ * single kernel, the class predicted fastest among those that apply to
+ * key_bits (the class holding the autotuned default tile shape stays the
+ * choice unless another is predicted faster by more than about 2%), then a
  * synchronisation of `stream` to read the choice (written by the kernel to
  * pinned host memory). A NULL model (or n == 0) yields the library default
  * (fields 0). cfg_out->key_type and cfg_out->descending are read on input
@@ -412,6 +436,32 @@ onesweep_status_t onesweep_select_config(const onesweep_model_t *model, const vo
                                          size_t n, int key_bits, int begin_bit, int end_bit,
                                          int has_values, onesweep_config_t *cfg_out,
                                          onesweep_stream_t stream);
+
+/* Sort with a learned configuration: onesweep_sort_keys (d_vals_in and
+ * d_vals_out NULL) or onesweep_sort_pairs, with the binning tile shape and
+ * ranking method picked by the model for these keys. For 2^26 <= n <= 2^28
+ * the model's selection kernel (features and forward pass, as in
+ * onesweep_select_config) runs on a stream owned by the model, forked from
+ * `stream` with an event, while the sort's clear, histogram and
+ * exclusive-sum kernels run on `stream`; the host then waits for the
+ * selection only (an event, not the stream) and enqueues the binning passes
+ * with the chosen shape, so the selection overlaps the first phases. The
+ * autotuned default (the class holding the default tile shape) stays the
+ * choice unless another class is predicted faster by more than about 2%.
+ * Outside that size range, with a NULL model, or with cfg->algorithm set to
+ * reduce-then-scan, the call is the plain sort with the default table and no
+ * selection. The output is the same whatever is chosen (the stable order is
+ * unique). cfg: key_type, descending, strip_log2 and trace are used; the tile
+ * fields are ignored. *cfg_used (may be NULL) receives the configuration
+ * the passes ran with. Temp storage as in onesweep_sort_keys (size query
+ * with d_temp == NULL covers every class). Synchronises on the selection
+ * event, so not graph-capturable; calls on one model must not overlap. */
+onesweep_status_t onesweep_sort_learned(const onesweep_model_t *model, void *d_temp,
+                                        size_t *temp_bytes, const void *d_keys_in,
+                                        void *d_keys_out, const uint32_t *d_vals_in,
+                                        uint32_t *d_vals_out, size_t n, int key_bits,
+                                        int begin_bit, int end_bit, const onesweep_config_t *cfg,
+                                        onesweep_config_t *cfg_used, onesweep_stream_t stream);
 
 /* Binning tile size T = block_threads x items_per_thread that `cfg` resolves
  * to for this key width, value presence and n; 0 if the config is

@@ -50,7 +50,8 @@ class Config(ctypes.Structure):
                 ("rank_algorithm", ctypes.c_int), ("segment_limits", ctypes.c_int * 3),
                 ("segment_streams", ctypes.c_int), ("algorithm", ctypes.c_int),
                 ("key_type", ctypes.c_int), ("descending", ctypes.c_int),
-                ("strip_log2", ctypes.c_int), ("trace", ctypes.POINTER(Trace))]
+                ("strip_log2", ctypes.c_int), ("lookback_spin_limit", ctypes.c_int),
+                ("trace", ctypes.POINTER(Trace))]
 
 
 _vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
@@ -107,11 +108,11 @@ KEY_UNSIGNED, KEY_SIGNED, KEY_FLOAT = 0, 1, 2
 def make_config(block_threads: int = 0, items_per_thread: int = 0, hist_blocks_per_cu: int = 0,
                 digit_bits: int = 0, rank_algorithm: int = 0, segment_limits=(0, 0, 0),
                 segment_streams: int = 0, algorithm: int = 0, key_type: int = 0,
-                descending: bool = False, strip_log2: int = 0,
+                descending: bool = False, strip_log2: int = 0, lookback_spin_limit: int = 0,
                 trace: Trace | None = None) -> Config:
     c = Config(digit_bits, block_threads, items_per_thread, hist_blocks_per_cu, rank_algorithm,
                (ctypes.c_int * 3)(*segment_limits), segment_streams, algorithm, key_type,
-               int(descending), strip_log2, None)
+               int(descending), strip_log2, lookback_spin_limit, None)
     if trace is not None:
         c.trace = ctypes.pointer(trace)
     return c
@@ -421,10 +422,13 @@ _lib.onesweep_model_gradients.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp, _v
 _lib.onesweep_model_train_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, _vp,
                                            _vp]
 _lib.onesweep_select_config.argtypes = [_vp, _vp, _sz, _i32, _i32, _i32, _i32, _cfgp, _vp]
+_lib.onesweep_sort_learned.argtypes = [_vp, _vp, _szp, _vp, _vp, _vp, _vp, _sz, _i32, _i32, _i32,
+                                       _cfgp, _cfgp, _vp]
 for _f in ("onesweep_model_create", "onesweep_model_load", "onesweep_model_save",
            "onesweep_model_set_params", "onesweep_model_get_params", "onesweep_model_class",
            "onesweep_features", "onesweep_model_infer", "onesweep_model_forward",
-           "onesweep_model_gradients", "onesweep_model_train_step", "onesweep_select_config"):
+           "onesweep_model_gradients", "onesweep_model_train_step", "onesweep_select_config",
+           "onesweep_sort_learned"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -529,6 +533,36 @@ class Model:
     def select_config(self, keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
                       has_values: bool = False, stream=None) -> Config:
         return select_config(self, keys, begin_bit, end_bit, has_values, stream)
+
+
+def sort_learned(model: Model | None, keys: torch.Tensor, values: torch.Tensor | None = None,
+                 begin_bit: int = 0, end_bit: int | None = None, out: torch.Tensor | None = None,
+                 values_out: torch.Tensor | None = None, temp: torch.Tensor | None = None,
+                 config: Config | None = None, stream=None, descending: bool = False):
+    """Sort keys (and values) with the tile configuration the model picks for
+    them; the selection overlaps the sort's first phases (2^26..2^28 keys,
+    else the default table). Returns (keys_out, values_out or None, the
+    configuration the passes ran with)."""
+    kb = _key_bits(keys)
+    config = _ordered_config(config, keys, descending)
+    end_bit = kb if end_bit is None else end_bit
+    n = keys.numel()
+    out = torch.empty_like(keys) if out is None else out
+    if values is not None and values_out is None:
+        values_out = torch.empty_like(values)
+    h = None if model is None else model.handle
+    size = ctypes.c_size_t(0)
+    dummy = ctypes.c_void_p(4) if values is not None else None
+    _check(_lib.onesweep_sort_learned(h, None, ctypes.byref(size), None, None, dummy, dummy, n,
+                                      kb, begin_bit, end_bit, _cfg_ptr(config), None, None))
+    temp = _temp(temp, int(size.value), keys.device)
+    size = ctypes.c_size_t(temp.numel())
+    used = Config()
+    _check(_lib.onesweep_sort_learned(h, _dev_ptr(temp), ctypes.byref(size), _dev_ptr(keys),
+                                      _dev_ptr(out), _dev_ptr(values), _dev_ptr(values_out), n,
+                                      kb, begin_bit, end_bit, _cfg_ptr(config),
+                                      ctypes.byref(used), _stream(stream)))
+    return out, values_out, used
 
 
 def select_config(model: Model | None, keys: torch.Tensor, begin_bit: int = 0,

@@ -37,10 +37,21 @@ constexpr size_t kAlign = 256;
 constexpr size_t kMaxN = size_t(1) << 30;  // 30-bit status values, one chained scan
 // Whole plain sorts run large inputs as strips of at most 2^29 keys per
 // binning pass (each strip its own chained scan), so 30-bit status values
-// never overflow; 32-bit element indices keep a factor-2 headroom below 2^31.
-// (2^29 rather than the paper's 2^28: tiles of 1024 x 11 keys do not divide
-// 2^28, and a 2^28-key sort should stay one strip.)
-constexpr size_t kMaxSortN = size_t(1) << 31;
+// never overflow. (2^29 rather than the paper's 2^28: tiles of 1024 x 11 keys
+// do not divide 2^28, and a 2^28-key sort should stay one strip.) Below 2^31
+// elements, counts, bin starts and element positions are 32-bit (a factor-2
+// headroom in every 32-bit index computation); from 2^31 on they are 64-bit
+// (Section 3, handling very large problems: 64-bit global histogram counts
+// and carried bin starts), the upfront histogram runs over portions of at
+// most 2^30 keys (32-bit counters in LDS) and adds into 64-bit global counts.
+// 2^36 elements (256 GiB of 32-bit keys) is beyond one GPU's memory.
+constexpr size_t kWideN = size_t(1) << 31;
+constexpr size_t kMaxSortN = size_t(1) << 36;
+constexpr size_t kHistPortion = size_t(1) << 30;
+// A late tile choice (the learned selector) applies to at most 2^28 keys:
+// then every tile of at most 65536 keys bins each place in one strip, so
+// only the status region depends on the tile.
+constexpr size_t kLateChoiceMaxN = size_t(1) << 28;
 constexpr int kDefaultStripLog2 = 29;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -79,8 +90,14 @@ struct Resolved {
   int strip_log2;
   int algorithm;  // onesweep_algorithm_t
   KeyOrder order;
+  uint32_t spin_limit;  // look-back polls without an inclusive prefix before giving up
   onesweep_trace_t *trace;
 };
+
+// Default bound of the look-back wait: 2^22 polls of a tile's window of
+// predecessors, each a memory round trip of a microsecond or more, so
+// seconds; a legitimate look-back takes a few polls.
+constexpr uint32_t kDefaultSpinLimit = 1u << 22;
 
 // Constants of the order transform for a key width, key type and direction;
 // `pad` is the key whose transformed bits are all ones (the largest digit at
@@ -107,10 +124,14 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
                           Resolved *r, Caller caller = kCallOther) {
   r->shape = caller == kCallSegments ? segment_default_shape(key_bits, has_values)
                                      : binning_default_shape(key_bits, has_values, n);
-  r->hist_blocks_per_cu = key_bits == 64 ? 2 : 4;
+  // The histogram's 1024-thread workgroups use 64 KiB of LDS each, so two
+  // fit a CU: a grid of two per CU is resident at once (at 2^28 u32 keys
+  // 244 us against 250 us with four per CU, which runs in two rounds).
+  r->hist_blocks_per_cu = 2;
   r->algorithm = ONESWEEP_ALGORITHM_ONESWEEP;
   r->strip_log2 = kDefaultStripLog2;
   r->order = key_order(key_bits, ONESWEEP_KEY_UNSIGNED, false);
+  r->spin_limit = kDefaultSpinLimit;
   r->trace = nullptr;
   if (cfg != nullptr) {
     if (cfg->digit_bits != 0 && cfg->digit_bits != kRadixBits)
@@ -143,6 +164,10 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
       return fail(ONESWEEP_ERROR_INVALID_VALUE, "descending %d not 0 or 1", cfg->descending);
     if (key_bits == 32 || key_bits == 64)
       r->order = key_order(key_bits, cfg->key_type, cfg->descending != 0);
+    if (cfg->lookback_spin_limit < 0)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "lookback_spin_limit %d is negative",
+                  cfg->lookback_spin_limit);
+    if (cfg->lookback_spin_limit != 0) r->spin_limit = static_cast<uint32_t>(cfg->lookback_spin_limit);
     r->trace = cfg->trace;
     if (r->trace && (r->trace->capacity < 0 || r->trace->capacity > ONESWEEP_TRACE_MAX ||
                      (r->trace->capacity > 0 && r->trace->events == nullptr)))
@@ -150,11 +175,16 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
   }
   const bool rts = r->algorithm == ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN;
   const int mode = caller == kCallSegments ? kBinSegmented : (rts ? kBinDownsweep : kBinChained);
-  if (!binning_shape_supported(r->shape, mode) ||
+  const bool wide = caller == kCallSort && n >= kWideN;
+  if (wide && rts)
+    return fail(ONESWEEP_ERROR_UNSUPPORTED,
+                "reduce-then-scan is built for n below 2^31 (n = %zu)", n);
+  if (!binning_shape_supported(r->shape, mode, wide) ||
       (rts && !upsweep_shape_supported(key_bits, r->shape.block, r->shape.ipt)))
     return fail(ONESWEEP_ERROR_UNSUPPORTED,
                 "%sbinning shape (key_bits=%d, values=%d, block=%d, items=%d, rank=%d) not built",
-                mode == kBinSegmented ? "segmented " : (rts ? "reduce-then-scan " : ""),
+                mode == kBinSegmented ? "segmented "
+                                      : (rts ? "reduce-then-scan " : (wide ? "64-bit-position " : "")),
                 key_bits, (int)has_values, r->shape.block, r->shape.ipt, r->shape.rank + 1);
   return ONESWEEP_SUCCESS;
 }
@@ -167,6 +197,7 @@ struct SortLayout {
   uint32_t tiles;
   uint32_t strip_tiles, strips;  // tiles per strip, strips per binning pass
   size_t status_words_per_place;
+  size_t tiles_for_layout;       // the tile size the layout was computed for
 };
 
 // Reduce-then-scan keeps one count table of the same size as a place's
@@ -176,9 +207,15 @@ struct SortLayout {
 // tiles, at least one); strip k > 0 of place j reads its bin starts from
 // strip_offsets[(j * strips + k) * 256], written by strip k - 1. Each
 // (place, strip) has its own tile counter.
+// With a late tile choice (`late_status`), the status rows go last, sized for
+// `tile` (the smallest choice), and are not part of the first cleared
+// region: they are cleared once the tile is chosen, as many as it needs.
 SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size_t tile,
-                       bool rts = false, int strip_log2 = kDefaultStripLog2) {
+                       bool rts = false, int strip_log2 = kDefaultStripLog2,
+                       bool late_status = false) {
   SortLayout L{};
+  L.tiles_for_layout = tile;
+  const size_t cw = n >= kWideN ? 8 : 4;  // bytes of a count, offset or bin start
   L.tiles = static_cast<uint32_t>((n + tile - 1) / tile);
   L.status_words_per_place = static_cast<size_t>(L.tiles) * kRadix;
   L.strip_tiles = static_cast<uint32_t>(std::max<size_t>(1, (size_t(1) << strip_log2) / tile));
@@ -186,28 +223,33 @@ SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size
   if (rts) L.strip_tiles = std::max<uint32_t>(L.tiles, 1u);
   size_t off = 0;
   L.hist = off;
-  off += align_up(sizeof(uint32_t) * kMaxPlaces * kRadix);
+  off += align_up(cw * kMaxPlaces * kRadix);
   L.counters = off;
   off += align_up(sizeof(uint32_t) * static_cast<size_t>(std::max(places, 1)) * L.strips);
   L.status = off;
-  if (rts) {
+  if (rts || late_status) {
     L.zero_end = off;
-    off += align_up(sizeof(uint32_t) * L.status_words_per_place * (places > 0 ? 1 : 0));
+    if (!late_status)
+      off += align_up(sizeof(uint32_t) * L.status_words_per_place * (places > 0 ? 1 : 0));
   } else {
     off += align_up(sizeof(uint32_t) * L.status_words_per_place * places);
     L.zero_end = off;
   }
   L.offsets = off;
-  off += align_up(sizeof(uint32_t) * kMaxPlaces * kRadix);
+  off += align_up(cw * kMaxPlaces * kRadix);
   L.strip_offsets = off;
   if (L.strips > 1)
-    off += align_up(sizeof(uint32_t) * kRadix * static_cast<size_t>(places) * L.strips);
+    off += align_up(cw * kRadix * static_cast<size_t>(places) * L.strips);
   L.plan = off;
   off += kAlign;
   L.tmp_keys = off;
   off += align_up(n * (key_bits / 8));
   L.tmp_vals = off;
   if (has_values) off += align_up(n * sizeof(uint32_t));
+  if (late_status) {
+    L.status = off;
+    off += align_up(sizeof(uint32_t) * L.status_words_per_place * places);
+  }
   L.total = off;
   return L;
 }
@@ -257,23 +299,31 @@ onesweep_status_t check_common(size_t *temp_bytes, size_t n, int key_bits, int b
                 begin_bit, end_bit, key_bits);
   if (n >= max_n)
     return fail(ONESWEEP_ERROR_TOO_LARGE, "n = %zu is not below 2^%d", n,
-                max_n == kMaxSortN ? 31 : 30);
+                max_n == kMaxSortN ? 36 : 30);
   return ONESWEEP_SUCCESS;
 }
 
 onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_in,
                             void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
                             bool has_values, size_t n, int key_bits, int begin_bit, int end_bit,
-                            const onesweep_config_t *cfg, hipStream_t stream) {
+                            const onesweep_config_t *cfg, hipStream_t stream,
+                            const LateChoice *late = nullptr) {
   g_error[0] = '\0';
   onesweep_status_t st = check_common(temp_bytes, n, key_bits, begin_bit, end_bit, kMaxSortN);
   if (st) return st;
   Resolved rc;
   if ((st = resolve(key_bits, has_values, n, cfg, &rc, kCallSort))) return st;
   const int places = num_places(begin_bit, end_bit);
-  const size_t tile = binning_tile_items(rc.shape);
+  size_t tile = binning_tile_items(rc.shape);
   const bool rts = rc.algorithm == ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN;
-  const SortLayout L = sort_layout(n, key_bits, has_values, places, tile, rts, rc.strip_log2);
+  if (late && (rts || n > kLateChoiceMaxN || late->layout_tile == 0))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "late tile choice needs Onesweep and n <= 2^28");
+  // Temporary storage: laid out for the smallest tile a late choice can make
+  // (most tiles, so the largest status region); at most 2^28 keys, one strip
+  // whatever the tile.
+  const SortLayout L = sort_layout(n, key_bits, has_values, places,
+                                   late ? std::min(tile, late->layout_tile) : tile, rts,
+                                   rc.strip_log2, late != nullptr);
   if (d_temp == nullptr) {
     *temp_bytes = L.total;
     return ONESWEEP_SUCCESS;
@@ -327,7 +377,7 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
   ca.vals[kBufIn] = const_cast<uint32_t *>(vals_in);
   ca.vals[kBufOut] = vals_out;
   ca.vals[kBufTmp] = has_values ? reinterpret_cast<uint32_t *>(temp + L.tmp_vals) : nullptr;
-  ca.n = static_cast<uint32_t>(n);
+  ca.n = n;
   ca.key_bytes = static_cast<int>(kb);
 
   if (places == 0) {  // empty bit range: the sorted order is the input order
@@ -337,31 +387,64 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
     return ONESWEEP_SUCCESS;
   }
 
-  uint32_t *hist = reinterpret_cast<uint32_t *>(temp + L.hist);
+  // Sorts of 2^31 elements or more keep 64-bit counts and bin offsets.
+  const bool wide = n >= kWideN;
+  uint32_t *hist = wide ? nullptr : reinterpret_cast<uint32_t *>(temp + L.hist);
+  unsigned long long *hist64 =
+      wide ? reinterpret_cast<unsigned long long *>(temp + L.hist) : nullptr;
   uint32_t *counters = reinterpret_cast<uint32_t *>(temp + L.counters);
   uint32_t *status = reinterpret_cast<uint32_t *>(temp + L.status);
-  uint32_t *offsets = reinterpret_cast<uint32_t *>(temp + L.offsets);
+  uint32_t *offsets = wide ? nullptr : reinterpret_cast<uint32_t *>(temp + L.offsets);
+  unsigned long long *offsets64 =
+      wide ? reinterpret_cast<unsigned long long *>(temp + L.offsets) : nullptr;
   PassPlan *plan = reinterpret_cast<PassPlan *>(temp + L.plan);
 
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "clear",
                   launch_fill_zero(temp + L.hist, L.zero_end - L.hist, stream_grid, stream));
-  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
-                  launch_histogram(key_bits, keys_in, hist, static_cast<uint32_t>(n), begin_bit,
-                                   end_bit, places, rc.order,
-                                   static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), stream));
+  // Histogram portions of at most 2^30 keys (one launch below 2^30 keys).
+  for (size_t done = 0; done < n; done += kHistPortion) {
+    const size_t part = std::min(kHistPortion, n - done);
+    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
+                    launch_histogram(key_bits, static_cast<const char *>(keys_in) + done * kb,
+                                     hist, hist64, static_cast<uint32_t>(part), begin_bit,
+                                     end_bit, places, rc.order,
+                                     static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), stream));
+  }
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_SCAN, "scan",
-                  launch_scan(hist, offsets, plan, places, static_cast<uint32_t>(n), alias,
-                              stream));
-  uint32_t *strip_offsets = reinterpret_cast<uint32_t *>(temp + L.strip_offsets);
+                  launch_scan(hist, hist64, offsets, offsets64, plan, places, n, alias, stream));
+  if (late) {
+    // The binning tile shape is decided now, while the kernels above run.
+    onesweep_config_t c = cfg ? *cfg : onesweep_config_t{};
+    if ((st = late->choose(late->ctx, &c))) return st;
+    Resolved picked;
+    if ((st = resolve(key_bits, has_values, n, &c, &picked, kCallSort))) return st;
+    if (binning_tile_items(picked.shape) < L.tiles_for_layout)
+      return fail(ONESWEEP_ERROR_INVALID_VALUE, "chosen tile below the laid-out tile");
+    rc.shape = picked.shape;
+    tile = binning_tile_items(rc.shape);
+  }
+  // Launch geometry of the binning passes (the regions are L's).
+  const SortLayout G = sort_layout(n, key_bits, has_values, places, tile, rts, rc.strip_log2);
+  // With a late choice the status rows of every place are packed for the
+  // chosen tile and cleared now, only as many as it needs.
+  const size_t status_stride = late ? G.status_words_per_place : L.status_words_per_place;
+  if (late)
+    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "clear",
+                    launch_fill_zero(status, sizeof(uint32_t) * status_stride * places,
+                                     stream_grid, stream));
   // One place: the reduce-then-scan upsweep and tile scan when that algorithm
-  // runs, then the binning (or downsweep) launches, one per strip.
-  auto bin_place = [&](auto key_tag, int j) -> onesweep_status_t {
+  // runs, then the binning (or downsweep) launches, one per strip. Idx is the
+  // type of element positions, counts and bin offsets.
+  auto bin_place = [&](auto key_tag, auto idx_tag, int j) -> onesweep_status_t {
     using K = decltype(key_tag);
+    using Idx = decltype(idx_tag);
+    Idx *strip_offsets = reinterpret_cast<Idx *>(temp + L.strip_offsets);
+    const Idx *place_offsets = reinterpret_cast<const Idx *>(temp + L.offsets) + j * kRadix;
     const int lo = begin_bit + j * kRadixBits;
     const int width = (lo + kRadixBits <= end_bit) ? kRadixBits : end_bit - lo;
     // Onesweep: place j's own status words; reduce-then-scan: the shared
     // count table, filled by the upsweep and scanned before the downsweep.
-    uint32_t *table = rts ? status : status + j * L.status_words_per_place;
+    uint32_t *table = rts ? status : status + j * status_stride;
     if (rts) {
       UpsweepArgs<K> u{};
       for (int b = 0; b < 3; ++b) u.keys[b] = static_cast<K *>(ca.keys[b]);
@@ -373,42 +456,60 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
       u.shift = lo;
       u.width = width;
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_UPSWEEP, "upsweep",
-                      launch_upsweep(key_bits, rc.shape.block, rc.shape.ipt, &u, L.tiles,
+                      launch_upsweep(key_bits, rc.shape.block, rc.shape.ipt, &u, G.tiles,
                                      stream));
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_TILE_SCAN, "tile scan",
-                      launch_tile_scan(table, L.tiles, plan, j, stream));
+                      launch_tile_scan(table, G.tiles, plan, j, stream));
     }
-    uint32_t *place_strips = strip_offsets + static_cast<size_t>(j) * L.strips * kRadix;
-    for (uint32_t k = 0; k < L.strips; ++k) {
-      BinningArgs<K> a{};
+    Idx *place_strips = strip_offsets + static_cast<size_t>(j) * G.strips * kRadix;
+    for (uint32_t k = 0; k < G.strips; ++k) {
+      BinningArgs<K, Idx> a{};
       for (int b = 0; b < 3; ++b) a.keys[b] = static_cast<K *>(ca.keys[b]);
       for (int b = 0; b < 3; ++b) a.vals[b] = ca.vals[b];
-      a.bin_offsets = k == 0 ? offsets + j * kRadix : place_strips + k * kRadix;
-      a.next_bin_offsets = k + 1 < L.strips ? place_strips + (k + 1) * kRadix : nullptr;
-      a.tile_first = k * L.strip_tiles;
+      a.bin_offsets = k == 0 ? place_offsets : place_strips + k * kRadix;
+      a.next_bin_offsets = k + 1 < G.strips ? place_strips + (k + 1) * kRadix : nullptr;
+      a.tile_first = k * G.strip_tiles;
       a.status = table;
-      a.tile_counter = counters + static_cast<size_t>(j) * L.strips + k;
+      a.tile_counter = counters + static_cast<size_t>(j) * G.strips + k;
       a.plan = plan;
       a.order = rc.order;
-      a.n = static_cast<uint32_t>(n);
+      a.lookback_error = &plan->lookback_error;
+      a.spin_limit = rc.spin_limit;
+      a.n = static_cast<Idx>(n);
       a.place = j;
       a.shift = lo;
       a.width = width;
-      const uint32_t grid = std::min(L.strip_tiles, L.tiles - a.tile_first);
+      const uint32_t grid = std::min(G.strip_tiles, G.tiles - a.tile_first);
       ONESWEEP_LAUNCH(tr, rts ? ONESWEEP_KERNEL_DOWNSWEEP : ONESWEEP_KERNEL_BINNING, "binning",
                       launch_binning(rc.shape, rts ? kBinDownsweep : kBinChained, &a, grid,
-                                     stream));
+                                     stream, wide));
     }
     return ONESWEEP_SUCCESS;
   };
   for (int j = 0; j < places; ++j) {
-    st = key_bits == 32 ? bin_place(uint32_t{}, j) : bin_place(uint64_t{}, j);
+    if (key_bits == 32)
+      st = wide ? bin_place(uint32_t{}, uint64_t{}, j) : bin_place(uint32_t{}, uint32_t{}, j);
+    else
+      st = wide ? bin_place(uint64_t{}, uint64_t{}, j) : bin_place(uint64_t{}, uint32_t{}, j);
     if (st) return st;
   }
   ca.plan = plan;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_COPY, "copy", launch_copy(ca, stream_grid, stream));
   return ONESWEEP_SUCCESS;
 }
+
+}  // namespace
+
+onesweep_status_t sort_late_choice(void *d_temp, size_t *temp_bytes, const void *keys_in,
+                                   void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                                   bool has_values, size_t n, int key_bits, int begin_bit,
+                                   int end_bit, const onesweep_config_t *cfg, hipStream_t stream,
+                                   const LateChoice &late) {
+  return sort_impl(d_temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, has_values, n,
+                   key_bits, begin_bit, end_bit, cfg, stream, &late);
+}
+
+namespace {
 
 // ------------------------------------------------------------ segmented sort
 
@@ -752,6 +853,8 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
       a.tile_counter = counters + j;
       a.seg = seg;
       a.order = rc.order;
+      a.lookback_error = &plan->lookback_error;
+      a.spin_limit = rc.spin_limit;
       a.n = static_cast<uint32_t>(n);
       a.place = j;
       a.shift = lo;
@@ -768,6 +871,8 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
       a.tile_counter = counters + j;
       a.seg = seg;
       a.order = rc.order;
+      a.lookback_error = &plan->lookback_error;
+      a.spin_limit = rc.spin_limit;
       a.n = static_cast<uint32_t>(n);
       a.place = j;
       a.shift = lo;
@@ -909,8 +1014,8 @@ onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits,
                   launch_fill_zero(d_hist, sizeof(uint32_t) * places * kRadix, 1, s));
   if (n == 0) return ONESWEEP_SUCCESS;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
-                  launch_histogram(key_bits, d_keys, d_hist, static_cast<uint32_t>(n), begin_bit,
-                                   end_bit, places, rc.order,
+                  launch_histogram(key_bits, d_keys, d_hist, nullptr, static_cast<uint32_t>(n),
+                                   begin_bit, end_bit, places, rc.order,
                                    static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), s));
   return ONESWEEP_SUCCESS;
 }
@@ -979,6 +1084,8 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.tile_counter = counter;
     a.plan = nullptr;
     a.order = rc.order;
+    a.lookback_error = counter + 1;
+    a.spin_limit = rc.spin_limit;
     a.n = static_cast<uint32_t>(n);
     a.place = 0;
     a.shift = shift;
@@ -996,6 +1103,8 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     a.tile_counter = counter;
     a.plan = nullptr;
     a.order = rc.order;
+    a.lookback_error = counter + 1;
+    a.spin_limit = rc.spin_limit;
     a.n = static_cast<uint32_t>(n);
     a.place = 0;
     a.shift = shift;

@@ -58,6 +58,26 @@ constexpr bool kCheckedStores = ONESWEEP_CHECKED_STORES != 0;
 // Predecessor tiles read per look-back round trip.
 constexpr int kLookback = ONESWEEP_LOOKBACK_WINDOW;
 
+// Tile positions of a thread's keys, two 16-bit positions per register (a
+// tile holds at most 65536 keys). They live from the ranking to the last LDS
+// regroup; packed, the 1024 x 11 tile fits 64 registers, where unpacked one
+// key was spilled to scratch memory and reloaded right after a barrier, a
+// memory round trip on every tile's critical path. A position is set once
+// and then only grows by offsets that keep it below the tile size, so adding
+// to either half never carries into the other.
+template <int kN>
+struct PackedPos {
+  uint32_t w[(kN + 1) / 2];
+  __device__ __forceinline__ void set(int i, uint32_t v) {
+    if (i & 1) w[i >> 1] |= v << 16;
+    else w[i >> 1] = v;
+  }
+  __device__ __forceinline__ void add(int i, uint32_t v) { w[i >> 1] += v << (16 * (i & 1)); }
+  __device__ __forceinline__ uint32_t get(int i) const {
+    return (i & 1) ? (w[i >> 1] >> 16) : (w[i >> 1] & 0xFFFFu);
+  }
+};
+
 // Occupancy target (waves per SIMD the register allocation must allow).
 // 1024-thread workgroups always take 8 (64 registers): two of them per CU
 // keep twice the keys in flight of one, which outweighs a few spilled
@@ -75,11 +95,13 @@ constexpr int binning_waves_per_eu() {
 // step of reduce-then-scan: every tile's exclusive prefix per digit is read
 // from a table that the upsweep and tile-scan kernels filled beforehand.
 // kOrdered: keys are ranked by their ordered bits (signed, floating-point or
-// descending order); false for unsigned ascending sorts.
-template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode, bool kOrdered>
+// descending order); false for unsigned ascending sorts. Idx: type of element
+// positions (uint64_t for sorts of 2^31 elements or more).
+template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode, bool kOrdered,
+          typename Idx>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(binning_waves_per_eu<K, kBlock, kIpt>())))
-    binning_kernel(BinningArgs<K> a) {
+    binning_kernel(BinningArgs<K, Idx> a) {
   constexpr bool kSeg = kMode == kBinSegmented;
   constexpr bool kRts = kMode == kBinDownsweep;
   constexpr int kWaves = kBlock / kWave;
@@ -87,6 +109,7 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int kWaveItems = kWave * kIpt;
   static_assert(kBlock >= kRadix, "one thread per digit takes part in the look-back");
   static_assert(kBlock % kWave == 0, "whole wavefronts");
+  static_assert(kTile <= 65536, "tile positions are packed into 16 bits");
 
   uint32_t src_id = kBufIn, dst_id = kBufOut;
   if (a.plan != nullptr) {
@@ -111,7 +134,7 @@ __global__ void __launch_bounds__(kBlock)
   constexpr size_t kRankBytes = sizeof(uint32_t) * kWaves * kRadix * kEntryWords;
   constexpr size_t kStageBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
   __shared__ __attribute__((aligned(16))) unsigned char s_stage[kStageBytes];
-  __shared__ uint32_t s_gbase[kRadix];
+  __shared__ Idx s_gbase[kRadix];
   __shared__ uint32_t s_wave_sum[kRadix / kWave];
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_uniform;  // 1 + the tile's only digit, or 0
@@ -126,7 +149,7 @@ __global__ void __launch_bounds__(kBlock)
   const int shift = a.shift;
   const int width = a.width;
   const uint32_t mask = (1u << width) - 1u;
-  const uint32_t n = a.n;
+  const Idx n = a.n;
   auto digit = [&](K k) -> uint32_t {
     if constexpr (kOrdered) return digit_of(k, shift, mask, a.order);
     else return digit_of(k, shift, mask);
@@ -153,8 +176,9 @@ __global__ void __launch_bounds__(kBlock)
   }
   __syncthreads();
   const uint32_t tile = s_tile + a.tile_first;  // tickets count from the strip's start
-  uint32_t tile_base, tile_count, bin_base;
-  const uint32_t *bin_offsets;
+  Idx tile_base, bin_base;
+  uint32_t tile_count;
+  const Idx *bin_offsets;
   bool first;
   if constexpr (kSeg) {
     const uint4 info = a.seg.tile_info[tile];
@@ -164,36 +188,58 @@ __global__ void __launch_bounds__(kBlock)
     first = info.x == info.z;
     bin_offsets = a.seg.bin_offsets + (static_cast<size_t>(info.w) * a.seg.places + a.place) * kRadix;
   } else {
-    tile_base = tile * static_cast<uint32_t>(kTile);
-    tile_count = min(n - tile_base, static_cast<uint32_t>(kTile));
+    tile_base = static_cast<Idx>(tile) * static_cast<Idx>(kTile);
+    const Idx left = n - tile_base;
+    tile_count = left < static_cast<Idx>(kTile) ? static_cast<uint32_t>(left) : kTile;
     bin_base = 0u;
     first = tile == a.tile_first;
     bin_offsets = a.bin_offsets;
   }
-  const uint32_t tile_end = tile_base + tile_count;
+  const Idx tile_end = tile_base + tile_count;
   const bool full = tile_count == static_cast<uint32_t>(kTile);
 
-  // 1. Load. Lanes past the end get the key whose ordered bits are all ones:
-  // its digit is the largest one the place can hold and it ranks after every
-  // real key, so the padding occupies the last tile positions and is never
-  // written out.
+  // The bin starts of this place, loaded before the keys so that waiting for
+  // them does not wait for the keys; kept in s_gbase until the look-back.
+  Idx bin_start_load = 0u;
+  if (tid < kRadix) bin_start_load = bin_offsets[tid];
+
+  // 1. Load. For ranking, a lane past the end of a ragged tile holds the key
+  // whose ordered bits are all ones: its digit is the largest the place can
+  // hold and it ranks after every real key, so the padding occupies the last
+  // tile positions, which are never written out. Keys-only tiles load
+  // unconditionally (such lanes load the tile's last key, in bounds, and
+  // take the padding only when ranked), so no branch separates the loads
+  // from the ranking and each batch waits only for its own load; pairs load
+  // in two branches, which needs fewer registers where their values are live.
   K key[kIpt];
-  const uint32_t wave_base = tile_base + wave * kWaveItems + lane;
-  if (full) {
+  const Idx wave_base = tile_base + static_cast<uint32_t>(wave * kWaveItems + lane);
+  const K pad = kOrdered ? static_cast<K>(a.order.pad) : static_cast<K>(~K(0));
+  if constexpr (kVals) {
+    if (full) {
 #pragma unroll
-    for (int i = 0; i < kIpt; ++i) key[i] = src[wave_base + i * kWave];
+      for (int i = 0; i < kIpt; ++i) key[i] = src[wave_base + static_cast<uint32_t>(i * kWave)];
+    } else {
+#pragma unroll
+      for (int i = 0; i < kIpt; ++i) {
+        const Idx idx = wave_base + static_cast<uint32_t>(i * kWave);
+        key[i] = idx < tile_end ? src[idx] : pad;
+      }
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
-      const uint32_t idx = wave_base + i * kWave;
-      key[i] = idx < tile_end ? src[idx]
-                              : (kOrdered ? static_cast<K>(a.order.pad) : static_cast<K>(~K(0)));
+      const Idx idx = wave_base + static_cast<uint32_t>(i * kWave);
+      key[i] = src[full || idx < tile_end ? idx : tile_end - 1u];
     }
   }
+  if (tid < kRadix) s_gbase[tid] = bin_base + bin_start_load;
+  auto ranked = [&](int i) -> K {
+    return (full || wave_base + static_cast<uint32_t>(i * kWave) < tile_end) ? key[i] : pad;
+  };
 
   // 2. Wave64 multi-split ranking: pos[i] becomes the key's rank among the
   // wave's earlier keys with the same digit.
-  uint32_t pos[kIpt];
+  PackedPos<kIpt> pos;
   const uint32_t wave_table = static_cast<uint32_t>(wave) * kRadix * kEntryWords;
   if constexpr (kRank == kRankAtomic) {
     // Batch i's previous count is read back kDepth batches later, so only
@@ -204,10 +250,10 @@ __global__ void __launch_bounds__(kBlock)
     for (int i = 0; i < kIpt + kDepth; ++i) {
       if (i >= kDepth) {
         const int r = i - kDepth;
-        pos[r] += __shfl(prior[r], static_cast<int>(leader[r]), kWave);
+        pos.add(r, __shfl(prior[r], static_cast<int>(leader[r]), kWave));
       }
       if (i >= kIpt) continue;
-      const uint32_t d = digit(key[i]);
+      const uint32_t d = digit(ranked(i));
       uint32_t peers_lo = ~0u, peers_hi = ~0u;
 #pragma unroll
       for (int b = 0; b < kRadixBits; ++b) {
@@ -216,18 +262,19 @@ __global__ void __launch_bounds__(kBlock)
         peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
         peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
       }
-      pos[i] = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+      pos.set(i, below);
       leader[i] = peers_lo != 0u ? static_cast<uint32_t>(__builtin_ctz(peers_lo))
                                  : 32u + static_cast<uint32_t>(__builtin_ctz(peers_hi));
       prior[i] = 0u;
-      if (pos[i] == 0u)
+      if (below == 0u)
         prior[i] = atomicAdd(&s_rank[wave_table + d],
                              static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi)));
     }
   } else {
 #pragma unroll
   for (int i = 0; i < kIpt; ++i) {
-    const uint32_t d = digit(key[i]);
+    const uint32_t d = digit(ranked(i));
     const uint32_t e = wave_table + d * kEntryWords;
     uint32_t peers_lo, peers_hi;
     if constexpr (kRank == kRankPresence) {
@@ -251,7 +298,12 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
     const uint32_t prior = s_rank[e];
-    pos[i] = prior + __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+    uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+    // Count the peers below this lane now: left to the scheduler, the count
+    // sinks to after the last batch and keeps every batch's two peer masks
+    // live, which spills keys to scratch memory.
+    asm volatile("" : "+v"(below));
+    pos.set(i, prior + below);
     // Every lane of the group stores the same new count (and clears the
     // presence mask), so the result does not depend on which store lands.
     const uint32_t next = prior + static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi));
@@ -303,7 +355,7 @@ __global__ void __launch_bounds__(kBlock)
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kIpt; ++i)
-    pos[i] += s_rank[wave_table + digit(key[i]) * kEntryWords];
+    pos.add(i, s_rank[wave_table + digit(ranked(i)) * kEntryWords]);
   __syncthreads();  // the rank tables are dead; the region now holds the tile
   const uint32_t uniform = kShortCircuit ? s_uniform : 0u;
 
@@ -311,7 +363,7 @@ __global__ void __launch_bounds__(kBlock)
   // digit: its sorted order is its input order).
   if (uniform == 0u) {
 #pragma unroll
-    for (int i = 0; i < kIpt; ++i) s_keys[pos[i]] = key[i];
+    for (int i = 0; i < kIpt; ++i) s_keys[pos.get(i)] = key[i];
   }
 
   uint32_t val[kVals ? kIpt : 1];
@@ -319,7 +371,7 @@ __global__ void __launch_bounds__(kBlock)
     const uint32_t *__restrict__ vsrc = a.vals[src_id];
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
-      const uint32_t idx = wave_base + i * kWave;
+      const Idx idx = wave_base + static_cast<uint32_t>(i * kWave);
       val[i] = (full || idx < tile_end) ? vsrc[idx] : 0u;
     }
   }
@@ -329,15 +381,16 @@ __global__ void __launch_bounds__(kBlock)
   // trip reads a window of kLookback predecessors at once; tiles before the
   // first one read as an inclusive prefix of zero.
   if (tid < kRadix) {
-    const uint32_t bin_start = bin_base + bin_offsets[tid];
+    const Idx bin_start = s_gbase[tid];
     uint32_t exclusive = 0u;
     if constexpr (kRts) {
       // digit-major table of exclusive prefixes over tiles
-      const uint32_t tiles = (n + static_cast<uint32_t>(kTile) - 1u) / static_cast<uint32_t>(kTile);
+      const uint32_t tiles = static_cast<uint32_t>((n + static_cast<Idx>(kTile) - 1u) / static_cast<Idx>(kTile));
       exclusive = a.status[static_cast<size_t>(tid) * tiles + tile];
     } else if (!first) {
       int pred = static_cast<int>(tile) - 1;
       const int chain_first = static_cast<int>(a.tile_first);  // 0 in a segmented sort
+      uint32_t rounds = 0u;
       while (true) {
         uint32_t s[kLookback];
 #pragma unroll
@@ -361,6 +414,10 @@ __global__ void __launch_bounds__(kBlock)
           }
         }
         if (found) break;
+        if (++rounds >= a.spin_limit) {  // bounded wait: give up, record it
+          __hip_atomic_store(a.lookback_error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
         pred -= consumed;
         if (stalled) __builtin_amdgcn_s_sleep(1);
       }
@@ -380,33 +437,50 @@ __global__ void __launch_bounds__(kBlock)
   // 5b'. Short-circuit: every key of a one-digit tile goes to its bin at its
   // input position, straight from registers.
   if (uniform != 0u) {
-    const uint32_t g0 = s_gbase[uniform - 1u] + static_cast<uint32_t>(wave * kWaveItems + lane);
+    const Idx g0 = s_gbase[uniform - 1u] + static_cast<uint32_t>(wave * kWaveItems + lane);
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
-      const uint32_t g = g0 + static_cast<uint32_t>(i * kWave);
+      const Idx g = g0 + static_cast<uint32_t>(i * kWave);
       if (!kCheckedStores || g < n) dst[g] = key[i];
     }
     if constexpr (kVals) {
       uint32_t *__restrict__ vdst = a.vals[dst_id];
 #pragma unroll
       for (int i = 0; i < kIpt; ++i) {
-        const uint32_t g = g0 + static_cast<uint32_t>(i * kWave);
+        const Idx g = g0 + static_cast<uint32_t>(i * kWave);
         if (!kCheckedStores || g < n) vdst[g] = val[i];
       }
     }
     return;
   }
 
-  // 5b. Write runs of keys to their bins.
-  uint32_t dst_idx[kVals ? kIpt : 1];
+  // 5b. Write runs of keys to their bins. Full keys-only tiles read all their
+  // keys and destinations from LDS before the first store, so the LDS
+  // latencies overlap instead of alternating with the stores (pairs hold
+  // their values in registers here and would spill).
+  Idx dst_idx[kVals ? kIpt : 1];
+  if (!kVals && full) {
+    K k[kIpt];
+    Idx g[kIpt];
 #pragma unroll
-  for (int i = 0; i < kIpt; ++i) {
-    const uint32_t q = i * kBlock + tid;
-    if (full || q < tile_count) {
-      const K k = s_keys[q];
-      const uint32_t g = s_gbase[digit(k)] + q;
-      if (!kCheckedStores || g < n) dst[g] = k;
-      if constexpr (kVals) dst_idx[i] = g;
+    for (int i = 0; i < kIpt; ++i) k[i] = s_keys[i * kBlock + tid];
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) g[i] = s_gbase[digit(k[i])] + static_cast<uint32_t>(i * kBlock + tid);
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+      if (!kCheckedStores || g[i] < n) dst[g[i]] = k[i];
+      if constexpr (kVals) dst_idx[i] = g[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+      const uint32_t q = i * kBlock + tid;
+      if (q < tile_count) {
+        const K k = s_keys[q];
+        const Idx g = s_gbase[digit(k)] + q;
+        if (!kCheckedStores || g < n) dst[g] = k;
+        if constexpr (kVals) dst_idx[i] = g;
+      }
     }
   }
 
@@ -415,7 +489,7 @@ __global__ void __launch_bounds__(kBlock)
     uint32_t *__restrict__ vdst = a.vals[dst_id];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kIpt; ++i) s_vals[pos[i]] = val[i];
+    for (int i = 0; i < kIpt; ++i) s_vals[pos.get(i)] = val[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
@@ -550,13 +624,25 @@ __global__ void __launch_bounds__(kBlock)
   X(uint64_t, false, 1024, 8, 0)     \
   X(uint64_t, true, 1024, 8, 0)
 
+// Shapes built with 64-bit element positions for sorts of 2^31 elements or
+// more: the default large-input shape of each key width and value presence.
+#define ONESWEEP_WIDE_SHAPES(X)   \
+  X(uint32_t, false, 1024, 11, 0) \
+  X(uint32_t, true, 1024, 11, 0)  \
+  X(uint64_t, false, 1024, 9, 0)  \
+  X(uint64_t, true, 1024, 8, 0)
+
 #define ONESWEEP_SHAPE_IS(K, V, B, I, R) \
   (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I && s.rank == R)
 
-bool binning_shape_supported(const BinningShape &s, int mode) {
+bool binning_shape_supported(const BinningShape &s, int mode, bool wide) {
 #define ONESWEEP_MATCH(K, V, B, I, R) \
   if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) return true;
-  if (mode == kBinSegmented) {
+  if (wide) {
+    if (mode == kBinChained) {
+      ONESWEEP_WIDE_SHAPES(ONESWEEP_MATCH)
+    }
+  } else if (mode == kBinSegmented) {
     ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_MATCH)
   } else if (mode == kBinDownsweep) {
     ONESWEEP_DOWNSWEEP_SHAPES(ONESWEEP_MATCH)
@@ -607,32 +693,41 @@ BinningShape segment_default_shape(int key_bits, bool has_values) {
 }
 
 hipError_t launch_binning(const BinningShape &s, int mode, const void *args, uint32_t grid,
-                          hipStream_t stream) {
-#define ONESWEEP_LAUNCH(K, V, B, I, R, MODE)                                              \
-  if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) {                                                  \
-    const BinningArgs<K> &a = *static_cast<const BinningArgs<K> *>(args);                  \
-    if (key_order_is_plain(a.order))                                                       \
-      hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, MODE, false>), dim3(grid), dim3(B), 0, \
-                         stream, a);                                                       \
-    else                                                                                   \
-      hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, MODE, true>), dim3(grid), dim3(B), 0, \
-                         stream, a);                                                       \
-    return hipGetLastError();                                                              \
+                          hipStream_t stream, bool wide) {
+#define ONESWEEP_LAUNCH_IDX(K, V, B, I, R, MODE, IDX)                                       \
+  if (ONESWEEP_SHAPE_IS(K, V, B, I, R)) {                                                    \
+    const BinningArgs<K, IDX> &a = *static_cast<const BinningArgs<K, IDX> *>(args);          \
+    if (key_order_is_plain(a.order))                                                         \
+      hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, MODE, false, IDX>), dim3(grid), dim3(B), \
+                         0, stream, a);                                                      \
+    else                                                                                     \
+      hipLaunchKernelGGL((binning_kernel<K, V, B, I, R, MODE, true, IDX>), dim3(grid), dim3(B), \
+                         0, stream, a);                                                      \
+    return hipGetLastError();                                                                \
   }
+#define ONESWEEP_LAUNCH(K, V, B, I, R, MODE) ONESWEEP_LAUNCH_IDX(K, V, B, I, R, MODE, uint32_t)
 #define ONESWEEP_LAUNCH_FLAT(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinChained)
 #define ONESWEEP_LAUNCH_SEG(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinSegmented)
 #define ONESWEEP_LAUNCH_DOWN(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinDownsweep)
-  if (mode == kBinSegmented) {
+#define ONESWEEP_LAUNCH_WIDE(K, V, B, I, R) \
+  ONESWEEP_LAUNCH_IDX(K, V, B, I, R, kBinChained, uint64_t)
+  if (wide) {
+    if (mode == kBinChained) {
+      ONESWEEP_WIDE_SHAPES(ONESWEEP_LAUNCH_WIDE)
+    }
+  } else if (mode == kBinSegmented) {
     ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_LAUNCH_SEG)
   } else if (mode == kBinDownsweep) {
     ONESWEEP_DOWNSWEEP_SHAPES(ONESWEEP_LAUNCH_DOWN)
   } else {
     ONESWEEP_BINNING_SHAPES(ONESWEEP_LAUNCH_FLAT)
   }
+#undef ONESWEEP_LAUNCH_WIDE
 #undef ONESWEEP_LAUNCH_DOWN
 #undef ONESWEEP_LAUNCH_SEG
 #undef ONESWEEP_LAUNCH_FLAT
 #undef ONESWEEP_LAUNCH
+#undef ONESWEEP_LAUNCH_IDX
   return hipErrorInvalidValue;
 }
 

@@ -49,7 +49,8 @@ struct PassPlan {
   uint32_t dst[kMaxPlaces];
   uint32_t copy_src;  // buffer copied into the output at the end, or kNoBuffer
   uint32_t executed;
-  uint32_t pad[14];
+  uint32_t lookback_error;  // set to 1 by a binning pass whose look-back gave up
+  uint32_t pad[13];
 };
 static_assert(sizeof(PassPlan) <= 256, "plan fits one 256-byte slot");
 
@@ -66,7 +67,8 @@ struct SegmentPlan {
   uint32_t error;                      // 1: offsets invalid, nothing is sorted
   uint32_t count[kSegClasses + 1];     // segments per class (last: large)
   uint32_t large_tiles;                // binning tiles of all large segments
-  uint32_t pad[58];
+  uint32_t lookback_error;             // set to 1 by a binning pass whose look-back gave up
+  uint32_t pad[57];
 };
 static_assert(sizeof(SegmentPlan) == 256, "one 256-byte slot");
 
@@ -80,11 +82,15 @@ struct SegmentTiles {
   int places;
 };
 
-template <typename K>
+// Idx is the type of element positions: uint32_t below 2^31 elements,
+// uint64_t for larger sorts (Section 3, handling very large problems: 64-bit
+// global counts and carried bin starts; status words stay 30-bit because each
+// strip is its own chained scan of fewer than 2^30 keys).
+template <typename K, typename Idx = uint32_t>
 struct BinningArgs {
   K *keys[3];                  // in, out, tmp (in is only read)
   uint32_t *vals[3];           // same ids; unused for keys-only
-  const uint32_t *bin_offsets; // 256 global bin offsets of this place
+  const Idx *bin_offsets;      // 256 global bin offsets of this place
   uint32_t *status;            // [tiles][256] status words of this place
   uint32_t *tile_counter;      // dynamic tile ids of this place
   const PassPlan *plan;        // NULL: run unconditionally in -> out
@@ -95,8 +101,15 @@ struct BinningArgs {
   // scan, and its last tile writes bin_offsets + the strip's digit counts to
   // next_bin_offsets, the bin starts of the next strip (NULL: last strip).
   uint32_t tile_first;
-  uint32_t *next_bin_offsets;
-  uint32_t n;
+  Idx *next_bin_offsets;
+  // Bounded look-back wait: a tile that has polled its window of
+  // predecessors spin_limit times without reaching an inclusive prefix gives
+  // up, sets *lookback_error to 1 and carries on with what it has summed (its
+  // output is then wrong, but every workgroup exits). Legitimate look-backs
+  // take a few polls; the default limit is seconds of waiting.
+  uint32_t *lookback_error;
+  uint32_t spin_limit;
+  Idx n;
   int place;
   int shift;
   int width;
@@ -105,7 +118,8 @@ struct BinningArgs {
 template <typename K>
 struct HistogramArgs {
   const K *keys;
-  uint32_t *hist;  // [places][256], cleared before launch
+  uint32_t *hist;              // [places][256], cleared before launch
+  unsigned long long *hist64;  // if not NULL: 64-bit counts, added here instead
   uint32_t n;
   int begin_bit;
   int end_bit;

@@ -28,21 +28,41 @@ struct BinningShape {
   int rank;
 };
 
+// A binning configuration chosen on the host after the clear, histogram and
+// exclusive-sum kernels of a whole sort are enqueued (the learned selector
+// decides while they run): `choose` fills the tile fields (block_threads,
+// items_per_thread, rank_algorithm) of *cfg, which holds the caller's
+// configuration on entry; `layout_tile` is the smallest tile any choice can
+// make, which sizes the temporary storage. Onesweep only, n <= 2^28.
+struct LateChoice {
+  size_t layout_tile;
+  onesweep_status_t (*choose)(void *ctx, onesweep_config_t *cfg);
+  void *ctx;
+};
+onesweep_status_t sort_late_choice(void *d_temp, size_t *temp_bytes, const void *keys_in,
+                                   void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                                   bool has_values, size_t n, int key_bits, int begin_bit,
+                                   int end_bit, const onesweep_config_t *cfg, hipStream_t stream,
+                                   const LateChoice &late);
+
 // Binning kernel modes: Onesweep's chained scan over the tiles of one
 // sequence; the same per large segment of a segmented sort
 // (BinningArgs::seg); or the scatter (downsweep) step of the reduce-then-scan
 // baseline. Fewer shapes are built for the last two.
 enum BinningMode : int { kBinChained = 0, kBinSegmented = 1, kBinDownsweep = 2 };
 
-bool binning_shape_supported(const BinningShape &s, int mode);
+// `wide`: 64-bit element positions (sorts of 2^31 elements or more), built
+// for the default large-input shapes of the chained mode only.
+bool binning_shape_supported(const BinningShape &s, int mode, bool wide = false);
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n);
 BinningShape segment_default_shape(int key_bits, bool has_values);
 // Keys per binning tile of a shape.
 size_t binning_tile_items(const BinningShape &s);
 
-// `args` points to BinningArgs<uint32_t> or BinningArgs<uint64_t>.
+// `args` points to BinningArgs<K, Idx> with K the key type of the shape and
+// Idx uint64_t when `wide`, else uint32_t.
 hipError_t launch_binning(const BinningShape &s, int mode, const void *args,
-                          uint32_t grid, hipStream_t stream);
+                          uint32_t grid, hipStream_t stream, bool wide = false);
 
 // Reduce-then-scan baseline, per place: the upsweep counts every tile's
 // digits into a digit-major table [256][tiles]; the tile scan turns each
@@ -66,14 +86,20 @@ hipError_t launch_upsweep(int key_bits, int block, int ipt, const void *args, ui
 hipError_t launch_tile_scan(uint32_t *counts, uint32_t tiles, const PassPlan *plan, int place,
                             hipStream_t stream);
 
-// Histogram of all places (phase 1), persistent tile-cyclic grid.
-hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint32_t n,
-                            int begin_bit, int end_bit, int places, const KeyOrder &order,
-                            uint32_t grid, hipStream_t stream);
+// Histogram of all places (phase 1), persistent tile-cyclic grid, over
+// n < 2^31 keys; the counts are added to hist, or to the 64-bit hist64 when it
+// is not NULL (larger sorts histogram portions of the keys into it).
+hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist,
+                            unsigned long long *hist64, uint32_t n, int begin_bit, int end_bit,
+                            int places, const KeyOrder &order, uint32_t grid,
+                            hipStream_t stream);
 
-// Exclusive sums of every place's histogram and the pass plan (phase 2).
-hipError_t launch_scan(const uint32_t *hist, uint32_t *offsets, PassPlan *plan, int places,
-                       uint32_t n, bool alias, hipStream_t stream);
+// Exclusive sums of every place's histogram and the pass plan (phase 2):
+// 32-bit counts and offsets (hist, offsets), or 64-bit ones (hist64,
+// offsets64) when those are not NULL.
+hipError_t launch_scan(const uint32_t *hist, const unsigned long long *hist64, uint32_t *offsets,
+                       unsigned long long *offsets64, PassPlan *plan, int places, uint64_t n,
+                       bool alias, hipStream_t stream);
 
 // Copy of keys (and values) into the output. With a plan, the source buffer
 // is the plan's copy_src and nothing is copied when it is kNoBuffer; without
@@ -82,7 +108,7 @@ struct CopyArgs {
   void *keys[3];
   uint32_t *vals[3];
   const PassPlan *plan;
-  uint32_t n;
+  uint64_t n;
   int key_bytes;
 };
 hipError_t launch_copy(const CopyArgs &a, uint32_t grid, hipStream_t stream);
@@ -210,6 +236,11 @@ struct SelectArgs {
   int places;
   int has_values;
   uint32_t class_mask;
+  // The autotuned default's class (-1: none applies): it stays the choice
+  // unless another class is predicted faster by more than `margin` (in the
+  // predictions' log-time units).
+  int default_class;
+  float margin;
   float *out;         // kMlpClasses
   int *choice;        // device
   int *host_choice;   // mapped pinned host memory, may be NULL

@@ -238,6 +238,8 @@ __global__ void __launch_bounds__(1024) select_kernel(SelectArgs a) {
     int best = -1;
     for (int c = 0; c < kMlpClasses; ++c)
       if (((a.class_mask >> c) & 1u) && (best < 0 || s_out[c] < s_out[best])) best = c;
+    const int d = a.default_class;
+    if (d >= 0 && ((a.class_mask >> d) & 1u) && !(s_out[best] < s_out[d] - a.margin)) best = d;
     *a.choice = best;
     if (a.host_choice) *a.host_choice = best;
   }

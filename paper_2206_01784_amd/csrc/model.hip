@@ -50,6 +50,10 @@ struct onesweep_model {
   int *host_choice_dev;  // its device address
   int step;
   ModelClass classes[kMlpClasses];
+  // onesweep_sort_learned: the selection kernel runs on `aux`, forked from the
+  // caller's stream by `fork`; `picked` marks its end.
+  hipStream_t aux;
+  hipEvent_t fork, picked;
 };
 
 namespace {
@@ -101,7 +105,13 @@ onesweep_status_t create(int max_batch, onesweep_model **out) {
                                          hipHostMallocMapped);
   if (e == hipSuccess)
     e = hipHostGetDevicePointer(reinterpret_cast<void **>(&m->host_choice_dev), m->host_choice, 0);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->picked, hipEventDisableTiming);
   if (e != hipSuccess) {
+    if (m->picked) (void)hipEventDestroy(m->picked);
+    if (m->fork) (void)hipEventDestroy(m->fork);
+    if (m->aux) (void)hipStreamDestroy(m->aux);
     if (m->host_choice) (void)hipHostFree(m->host_choice);
     (void)hipFree(m->block);
     delete m;
@@ -233,6 +243,84 @@ onesweep_status_t check_batch(const onesweep_model *m, const void *a, const void
 
 }  // namespace
 
+namespace {
+
+// Selection applies to sorts of 2^26 to 2^28 keys. Below, the histogram
+// (under 60 us) is too short to hide the selection kernel and the host's wait
+// for it, and the autotuned table is what the measured sweep prefers; above,
+// every class would need strips of its own.
+constexpr size_t kLearnedMinN = size_t(1) << 26;
+constexpr size_t kLearnedMaxN = size_t(1) << 28;
+// A class replaces the autotuned default only when predicted faster by more
+// than this (log-time units, about 2%).
+constexpr float kSelectMargin = 0.02f;
+
+void class_fields(const ModelClass &c, onesweep_config_t *cfg) {
+  cfg->block_threads = c.block_threads;
+  cfg->items_per_thread = c.items_per_thread;
+  cfg->rank_algorithm = c.rank_algorithm;
+  cfg->hist_blocks_per_cu = c.hist_blocks_per_cu;
+}
+
+// The class holding the library's default tile shape for this input (ballot
+// ranking), or -1.
+int default_class(const onesweep_model_t *m, int key_bits, bool has_values, size_t n) {
+  const BinningShape d = binning_default_shape(key_bits, has_values, n);
+  for (int c = 0; c < kMlpClasses; ++c) {
+    const ModelClass &k = m->classes[c];
+    if ((k.key_bits_mask & (key_bits == 32 ? 1 : 2)) && k.block_threads == d.block &&
+        k.items_per_thread == d.ipt && k.rank_algorithm == 1 && k.hist_blocks_per_cu == 0)
+      return c;
+  }
+  return -1;
+}
+
+onesweep_status_t check_select(const onesweep_model_t *m, const void *d_keys, int key_bits,
+                               int begin_bit, int end_bit) {
+  if (key_bits != 32 && key_bits != 64)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "key_bits %d is not 32 or 64", key_bits);
+  if (begin_bit < 0 || begin_bit > end_bit || end_bit > key_bits)
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "bit range [%d, %d) invalid", begin_bit, end_bit);
+  if (!d_keys || (reinterpret_cast<uintptr_t>(d_keys) & (key_bits / 8 - 1)))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_keys NULL or not aligned to the key size");
+  (void)m;
+  return ONESWEEP_SUCCESS;
+}
+
+SelectArgs select_args(const onesweep_model_t *m, const void *d_keys, size_t n, int key_bits,
+                       int begin_bit, int end_bit, bool has_values) {
+  unsigned mask = 0;
+  for (int c = 0; c < kMlpClasses; ++c)
+    if (m->classes[c].key_bits_mask & (key_bits == 32 ? 1 : 2)) mask |= 1u << c;
+  SelectArgs a{};
+  a.params = m->params;
+  a.keys = d_keys;
+  a.n = n;
+  a.begin_bit = begin_bit;
+  a.end_bit = end_bit;
+  a.places = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+  a.has_values = has_values ? 1 : 0;
+  a.class_mask = mask;
+  a.default_class = default_class(m, key_bits, has_values, n);
+  a.margin = kSelectMargin;
+  a.out = m->infer_out;
+  a.choice = m->choice;
+  a.host_choice = m->host_choice_dev;
+  return a;
+}
+
+// The configuration of the class the last selection wrote to pinned host
+// memory (tile fields only; the rest of *cfg is kept); the default when no
+// class applied.
+onesweep_status_t chosen_class(const onesweep_model_t *m, onesweep_config_t *cfg) {
+  const int choice = *static_cast<volatile int *>(m->host_choice);
+  if (choice < 0 || choice >= kMlpClasses) return ONESWEEP_SUCCESS;
+  class_fields(m->classes[choice], cfg);
+  return ONESWEEP_SUCCESS;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t onesweep_model_num_params(void) { return static_cast<size_t>(kMlpParams); }
@@ -244,6 +332,9 @@ onesweep_status_t onesweep_model_create(int max_batch, onesweep_model_t **model)
 
 void onesweep_model_free(onesweep_model_t *model) {
   if (!model) return;
+  if (model->picked) (void)hipEventDestroy(model->picked);
+  if (model->fork) (void)hipEventDestroy(model->fork);
+  if (model->aux) (void)hipStreamDestroy(model->aux);
   (void)hipFree(model->block);
   if (model->host_choice) (void)hipHostFree(model->host_choice);
   delete model;
@@ -486,32 +577,92 @@ onesweep_status_t onesweep_select_config(const onesweep_model_t *m, const void *
   };
   memset(cfg_out, 0, sizeof(*cfg_out));
   if (!m || n == 0) return keep_order(ONESWEEP_SUCCESS);  // the library's default
-  if (begin_bit < 0 || begin_bit > end_bit || end_bit > key_bits)
-    return fail(ONESWEEP_ERROR_INVALID_VALUE, "bit range [%d, %d) invalid", begin_bit, end_bit);
-  if (!d_keys || (reinterpret_cast<uintptr_t>(d_keys) & (key_bits / 8 - 1)))
-    return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_keys NULL or not aligned to the key size");
-  unsigned mask = 0;
-  for (int c = 0; c < kMlpClasses; ++c)
-    if (m->classes[c].key_bits_mask & (key_bits == 32 ? 1 : 2)) mask |= 1u << c;
-  SelectArgs a{};
-  a.params = m->params;
-  a.keys = d_keys;
-  a.n = n;
-  a.begin_bit = begin_bit;
-  a.end_bit = end_bit;
-  a.places = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
-  a.has_values = has_values ? 1 : 0;
-  a.class_mask = mask;
-  a.out = m->infer_out;
-  a.choice = m->choice;
-  a.host_choice = m->host_choice_dev;
-  *m->host_choice = -1;
+  onesweep_status_t st = check_select(m, d_keys, key_bits, begin_bit, end_bit);
+  if (st) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  MLP_TRY(launch_select(key_bits, a, s), "select");
+  *m->host_choice = -1;
+  MLP_TRY(launch_select(key_bits, select_args(m, d_keys, n, key_bits, begin_bit, end_bit,
+                                              has_values != 0), s),
+          "select");
   MLP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  const int choice = *static_cast<volatile int *>(m->host_choice);
-  if (choice < 0 || choice >= kMlpClasses) return keep_order(ONESWEEP_SUCCESS);  // none applies
-  return keep_order(onesweep_model_class(m, choice, cfg_out, nullptr));
+  return keep_order(chosen_class(m, cfg_out));
+}
+
+onesweep_status_t onesweep_sort_learned(const onesweep_model_t *m, void *d_temp,
+                                        size_t *temp_bytes, const void *d_keys_in,
+                                        void *d_keys_out, const uint32_t *d_vals_in,
+                                        uint32_t *d_vals_out, size_t n, int key_bits,
+                                        int begin_bit, int end_bit, const onesweep_config_t *cfg,
+                                        onesweep_config_t *cfg_used, onesweep_stream_t stream) {
+  clear_error();
+  if (!temp_bytes) return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp_bytes is NULL");
+  if ((d_vals_in == nullptr) != (d_vals_out == nullptr))
+    return fail(ONESWEEP_ERROR_INVALID_VALUE, "value pointers: both or neither");
+  const bool has_values = d_vals_in != nullptr;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // The caller's configuration minus the tile fields, which are chosen here.
+  onesweep_config_t base = cfg ? *cfg : onesweep_config_t{};
+  base.block_threads = 0;
+  base.items_per_thread = 0;
+  base.rank_algorithm = 0;
+  if (cfg_used) *cfg_used = base;
+  const bool select = m != nullptr && n >= kLearnedMinN && n <= kLearnedMaxN &&
+                      (key_bits == 32 || key_bits == 64) && base.algorithm == 0;
+  if (!select) {  // the autotuned default table, without selection
+    return has_values ? onesweep_sort_pairs(d_temp, temp_bytes, d_keys_in, d_keys_out, d_vals_in,
+                                            d_vals_out, n, key_bits, begin_bit, end_bit, 1, &base,
+                                            stream)
+                      : onesweep_sort_keys(d_temp, temp_bytes, d_keys_in, d_keys_out, n, key_bits,
+                                           begin_bit, end_bit, 1, &base, stream);
+  }
+  // Temporary storage for the smallest tile any choice can make.
+  size_t layout_tile = onesweep_tile_items(key_bits, has_values, n, &base);
+  for (int c = 0; c < kMlpClasses; ++c) {
+    if (!(m->classes[c].key_bits_mask & (key_bits == 32 ? 1 : 2))) continue;
+    onesweep_config_t k = base;
+    class_fields(m->classes[c], &k);
+    const size_t t = onesweep_tile_items(key_bits, has_values, n, &k);
+    if (t != 0 && (layout_tile == 0 || t < layout_tile)) layout_tile = t;
+  }
+  if (layout_tile == 0) return fail(ONESWEEP_ERROR_UNSUPPORTED, "no built tile shape");
+  struct Ctx {
+    const onesweep_model_t *m;
+    onesweep_config_t picked;
+  } ctx{m, base};
+  LateChoice late{};
+  late.layout_tile = layout_tile;
+  late.ctx = &ctx;
+  late.choose = [](void *p, onesweep_config_t *c) -> onesweep_status_t {
+    Ctx &x = *static_cast<Ctx *>(p);
+    hipError_t e = hipEventSynchronize(x.m->picked);
+    if (e != hipSuccess) return hip_fail(e, "selection event");
+    onesweep_status_t st = chosen_class(x.m, c);
+    x.picked = *c;
+    return st;
+  };
+  if (d_temp == nullptr)  // size query: nothing is enqueued, choose is not called
+    return sort_late_choice(nullptr, temp_bytes, d_keys_in, d_keys_out, d_vals_in, d_vals_out,
+                            has_values, n, key_bits, begin_bit, end_bit, &base, s, late);
+  int dev = 0;
+  MLP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != m->device) return fail(ONESWEEP_ERROR_INVALID_VALUE, "model on device %d, current %d",
+                                    m->device, dev);
+  onesweep_status_t st = check_select(m, d_keys_in, key_bits, begin_bit, end_bit);
+  if (st) return st;
+  // The selection kernel reads the keys on the model's stream, after what the
+  // caller enqueued before, while the sort's clear, histogram and exclusive
+  // sums run on the caller's stream.
+  *m->host_choice = -1;
+  MLP_TRY(hipEventRecord(m->fork, s), "fork");
+  MLP_TRY(hipStreamWaitEvent(m->aux, m->fork, 0), "fork");
+  MLP_TRY(launch_select(key_bits, select_args(m, d_keys_in, n, key_bits, begin_bit, end_bit,
+                                              has_values), m->aux),
+          "select");
+  MLP_TRY(hipEventRecord(m->picked, m->aux), "select event");
+  st = sort_late_choice(d_temp, temp_bytes, d_keys_in, d_keys_out, d_vals_in, d_vals_out,
+                        has_values, n, key_bits, begin_bit, end_bit, &base, s, late);
+  if (st == ONESWEEP_SUCCESS && cfg_used) *cfg_used = ctx.picked;
+  return st;
 }
 
 }  // extern "C"

@@ -132,7 +132,10 @@ __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
     uint32_t sum = 0u;
 #pragma unroll
     for (int c = 0; c < kCopies; ++c) sum += s_hist[i * kCopies + c];
-    if (sum != 0u) atomicAdd(&a.hist[i], sum);
+    if (sum != 0u) {
+      if (a.hist64 != nullptr) atomicAdd(&a.hist64[i], static_cast<unsigned long long>(sum));
+      else atomicAdd(&a.hist[i], sum);
+    }
   }
 }
 
@@ -148,12 +151,13 @@ constexpr int kHistBlock = 1024;
 constexpr int kHistCopies32 = 16;
 constexpr int kHistCopies64 = 8;
 
-hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint32_t n,
-                            int begin_bit, int end_bit, int places, const KeyOrder &order,
-                            uint32_t grid, hipStream_t stream) {
+hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist,
+                            unsigned long long *hist64, uint32_t n, int begin_bit, int end_bit,
+                            int places, const KeyOrder &order, uint32_t grid,
+                            hipStream_t stream) {
   if (key_bits == 32) {
-    HistogramArgs<uint32_t> a{static_cast<const uint32_t *>(keys), hist, n, begin_bit, end_bit,
-                              places, order};
+    HistogramArgs<uint32_t> a{static_cast<const uint32_t *>(keys), hist, hist64, n, begin_bit,
+                              end_bit, places, order};
     if (key_order_is_plain(order))
       hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies32, false>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
@@ -161,8 +165,8 @@ hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint
       hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies32, true>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
   } else {
-    HistogramArgs<uint64_t> a{static_cast<const uint64_t *>(keys), hist, n, begin_bit, end_bit,
-                              places, order};
+    HistogramArgs<uint64_t> a{static_cast<const uint64_t *>(keys), hist, hist64, n, begin_bit,
+                              end_bit, places, order};
     if (key_order_is_plain(order))
       hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies64, false>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
@@ -178,28 +182,34 @@ hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist, uint
 // One workgroup of 256 threads: thread v owns digit v of every place. Besides
 // the global bin offsets, it marks a place trivial when one bin holds all n
 // keys (the pass would be the identity permutation) and lays out the buffer
-// route of the executed passes.
-__global__ void __launch_bounds__(kRadix) scan_kernel(const uint32_t *hist, uint32_t *offsets,
-                                                      PassPlan *plan, int places, uint32_t n,
+// route of the executed passes. Sums are taken in 64 bits; counts and offsets
+// are 32-bit words, or 64-bit ones when hist64 / offsets64 are given.
+__global__ void __launch_bounds__(kRadix) scan_kernel(const uint32_t *hist,
+                                                      const unsigned long long *hist64,
+                                                      uint32_t *offsets,
+                                                      unsigned long long *offsets64,
+                                                      PassPlan *plan, int places, uint64_t n,
                                                       int alias) {
-  __shared__ uint32_t s_wave_sum[kRadix / kWave];
+  __shared__ uint64_t s_wave_sum[kRadix / kWave];
   __shared__ uint32_t s_run[kMaxPlaces];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
   for (int j = 0; j < places; ++j) {
-    const uint32_t h = hist[j * kRadix + tid];
-    uint32_t incl = h;
+    const uint64_t h = hist64 != nullptr ? static_cast<uint64_t>(hist64[j * kRadix + tid])
+                                         : static_cast<uint64_t>(hist[j * kRadix + tid]);
+    uint64_t incl = h;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t t = __shfl_up(incl, off, kWave);
+      const uint64_t t = __shfl_up(incl, off, kWave);
       if (lane >= off) incl += t;
     }
     if (lane == kWave - 1) s_wave_sum[wave] = incl;
     const int trivial = __syncthreads_or(h == n);
-    uint32_t excl = incl - h;
+    uint64_t excl = incl - h;
     for (int w = 0; w < wave; ++w) excl += s_wave_sum[w];
-    offsets[j * kRadix + tid] = excl;
+    if (offsets64 != nullptr) offsets64[j * kRadix + tid] = excl;
+    else offsets[j * kRadix + tid] = static_cast<uint32_t>(excl);
     if (tid == 0) s_run[j] = trivial ? 0u : 1u;
     __syncthreads();  // s_wave_sum is reused by the next place
   }
@@ -230,15 +240,17 @@ __global__ void __launch_bounds__(kRadix) scan_kernel(const uint32_t *hist, uint
       p.copy_src = alias ? kNoBuffer : kBufIn;
     else
       p.copy_src = (cur == kBufOut) ? kNoBuffer : cur;
-    for (int i = 0; i < 14; ++i) p.pad[i] = 0u;
+    p.lookback_error = 0u;
+    for (int i = 0; i < 13; ++i) p.pad[i] = 0u;
     *plan = p;
   }
 }
 
-hipError_t launch_scan(const uint32_t *hist, uint32_t *offsets, PassPlan *plan, int places,
-                       uint32_t n, bool alias, hipStream_t stream) {
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kRadix), 0, stream, hist, offsets, plan, places,
-                     n, alias ? 1 : 0);
+hipError_t launch_scan(const uint32_t *hist, const unsigned long long *hist64, uint32_t *offsets,
+                       unsigned long long *offsets64, PassPlan *plan, int places, uint64_t n,
+                       bool alias, hipStream_t stream) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kRadix), 0, stream, hist, hist64, offsets,
+                     offsets64, plan, places, n, alias ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ import numpy as np
 import torch
 
 from . import (FEATURES, MODEL_CLASSES, Config, Model, OnesweepError, features, select_config,
-               sort_keys, sort_pairs, sort_temp_bytes, tile_items)
+               sort_keys, sort_learned, sort_pairs, sort_temp_bytes, tile_items)
 
 _ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if _ROOT not in sys.path:
@@ -189,11 +189,28 @@ def train(data_paths, out_path: str, steps: int = 3000, lr: float = 3e-3, seed: 
     return model, losses
 
 
-def evaluate(model_path: str | None, seeds, reps_scale: int = 1):
-    """Regret and gain of the model's choice over sweep inputs (keys only).
+def reference_sorted(keys: torch.Tensor) -> torch.Tensor:
+    """The keys sorted ascending as unsigned integers, by torch's own sort
+    (an implementation independent of this library): 32-bit keys widened to
+    int64, 64-bit keys with the sign bit flipped so signed order is unsigned
+    order."""
+    if keys.dtype == torch.uint32:
+        wide = keys.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        return torch.sort(wide).values.to(torch.int32).view(torch.uint32)
+    top = torch.tensor(-(1 << 63), dtype=torch.int64, device=keys.device)
+    flipped = keys.view(torch.int64) ^ top
+    return (torch.sort(flipped).values ^ top).view(torch.uint64)
 
-    regret = (selection time + sort time with the pick) / best class time - 1;
-    gain = default-config time / (selection time + sort time with the pick).
+
+def evaluate(model_path: str | None, seeds, reps_scale: int = 1):
+    """The learned sort against the library default over sweep inputs (keys
+    only). Per input: the default sort, the learned sort (selection included:
+    onesweep_sort_learned overlaps it with the first phases), the model's
+    pick timed without selection, and every class (for regret). Every output
+    of the learned sort is checked against torch's sort of the keys.
+
+    gain = default time / learned time; regret = learned time / best class
+    time - 1.
     """
     model = Model(max_batch=1, path=model_path) if model_path else None
     probe = Model(max_batch=1)
@@ -203,17 +220,22 @@ def evaluate(model_path: str | None, seeds, reps_scale: int = 1):
         keys, n, kb, dist = sweep_keys(seed)
         reps = reps_for(n) * reps_scale
         t, d, (out, _, temp) = time_classes(keys, kb, False, classes, reps)
-        cfg = select_config(model, keys, 0, kb, False)
-        # selection overhead: features + one forward pass + synchronisation
-        sel_ms = _timed(lambda: select_config(model, keys, 0, kb, False), reps)
-        pick_ms = _timed(lambda: sort_keys(keys, out=out, temp=temp, config=cfg), reps)
+        lout, _, used = sort_learned(model, keys)
+        torch.cuda.synchronize()
+        want = reference_sorted(keys)
+        if not torch.equal(lout.view(want.dtype), want):
+            raise RuntimeError(f"seed {seed}: the learned sort's output differs from torch.sort")
+        del want
+        ltemp = torch.empty(max(1, temp.numel()), dtype=torch.uint8, device=keys.device)
+        learned_ms = _timed(lambda: sort_learned(model, keys, out=lout), reps)
+        pick_ms = _timed(lambda: sort_keys(keys, out=out, temp=temp, config=used), reps)
         best = float(np.nanmin(t))
         rows.append(dict(seed=seed, n=n, key_bits=kb, dist=dist, best_ms=best, default_ms=d,
-                         pick_ms=pick_ms, select_ms=sel_ms,
-                         pick=[cfg.block_threads, cfg.items_per_thread, cfg.rank_algorithm]))
+                         learned_ms=learned_ms, pick_ms=pick_ms,
+                         pick=[used.block_threads, used.items_per_thread, used.rank_algorithm]))
         log(f"[eval] seed={seed} n={n} kb={kb} {dist}: best {best:.4f} default {d:.4f} "
-            f"pick {pick_ms:.4f} (+{sel_ms:.4f} select) ms")
-        del keys, out, temp
+            f"learned {learned_ms:.4f} (pick {pick_ms:.4f}) ms, pick {rows[-1]['pick']}")
+        del keys, out, temp, lout, ltemp
         torch.cuda.empty_cache()
     return summarize(rows), rows
 
@@ -221,18 +243,23 @@ def evaluate(model_path: str | None, seeds, reps_scale: int = 1):
 def summarize(rows):
     best = np.array([r["best_ms"] for r in rows])
     default = np.array([r["default_ms"] for r in rows])
+    learned = np.array([r["learned_ms"] for r in rows])
     pick = np.array([r["pick_ms"] for r in rows])
-    sel = np.array([r["select_ms"] for r in rows])
+    n = np.array([r["n"] for r in rows])
     geo = lambda a: float(np.exp(np.mean(np.log(a))))  # noqa: E731
-    return {
+    sel = n >= (1 << 26)
+    out = {
         "inputs": len(rows),
-        "regret_mean": float(np.mean((pick + sel) / best - 1)),
-        "regret_mean_without_selection": float(np.mean(pick / best - 1)),
-        "gain_geomean": geo(default / (pick + sel)),
+        "gain_geomean": geo(default / learned),
         "gain_geomean_without_selection": geo(default / pick),
+        "regret_mean": float(np.mean(learned / best - 1)),
         "best_over_default_geomean": geo(default / best),
-        "selection_ms_mean": float(np.mean(sel)),
+        "inputs_selected": int(sel.sum()),
     }
+    if sel.any():
+        out["gain_geomean_selected"] = geo(default[sel] / learned[sel])
+        out["best_over_default_geomean_selected"] = geo(default[sel] / best[sel])
+    return out
 
 
 def _seeds(spec: str):

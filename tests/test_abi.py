@@ -53,7 +53,7 @@ def test_temp_size_query_needs_no_gpu():
     (dict(key_bits=48), 1),
     (dict(begin_bit=9, end_bit=8), 1),
     (dict(end_bit=33), 1),
-    (dict(n=1 << 31), 2),
+    (dict(n=1 << 36), 2),
 ])
 def test_invalid_arguments_are_rejected_on_the_host(kwargs, code):
     import paper_2206_01784_amd as ow
@@ -144,9 +144,11 @@ def test_key_type_and_direction_validation_needs_no_gpu():
 
 
 def test_strip_configuration_and_size_limits_need_no_gpu():
-    """Whole plain sorts accept n up to 2^31 - 1 (strips of at most 2^29
-    keys per chained scan); the single-pass, histogram and segmented entry
-    points keep one chained scan and the 2^30 limit."""
+    """Whole plain sorts accept n below 2^36 (strips of at most 2^29 keys per
+    chained scan; from 2^31 keys on, 64-bit counts, bin starts and positions,
+    built for the default large-input tile shapes only, and no
+    reduce-then-scan); the single-pass, histogram and segmented entry points
+    keep one chained scan and the 2^30 limit."""
     import paper_2206_01784_amd as ow
     lib = ow.library()
     size = ctypes.c_size_t(0)
@@ -163,8 +165,21 @@ def test_strip_configuration_and_size_limits_need_no_gpu():
         rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
                                     ctypes.byref(cfg), None)
         assert rc == ow.ERROR_INVALID_VALUE, bad
-    assert lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 1 << 31, 32, 0, 32, 1,
+    assert lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 1 << 36, 32, 0, 32, 1,
                                   None, None) == ow.ERROR_TOO_LARGE
+    # 2^31 keys: 64-bit counts and bin offsets (8 bytes per entry), five strips
+    wide = ow.sort_temp_bytes(1 << 31, 32)
+    narrow = ow.sort_temp_bytes((1 << 31) - 1, 32)
+    assert wide - narrow >= 2 * 8 * 256 * 4 - 8 * 256 * 4
+    assert ow.sort_temp_bytes(1 << 31, 64, True) >= 12 * (1 << 31)
+    for kb, vals in ((32, False), (32, True), (64, False), (64, True)):
+        assert ow.tile_items(kb, vals, None, 1 << 31) > 0
+    for cfg in (ow.make_config(1024, 8), ow.make_config(algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)):
+        rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 1 << 31, 32, 0, 32, 1,
+                                    ctypes.byref(cfg), None)
+        assert rc == ow.ERROR_UNSUPPORTED
+        assert lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, (1 << 31) - 1, 32, 0,
+                                      32, 1, ctypes.byref(cfg), None) == 0
     assert lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, None, None, 1 << 30,
                                       None, 1, 32, 0, 32, 1, None,
                                       None) == ow.ERROR_TOO_LARGE

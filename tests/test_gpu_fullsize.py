@@ -1,10 +1,11 @@
 """GPU parity at the full benchmark sizes, in the launch configuration the
 benchmark times (default config): 2^28 uint32 keys (uniform, the entropy bands
 AND-of-2/3/4/8/16, all equal), 2^27 uint64 keys, 2^28 uint32 pairs and 2^27
-uint64-key pairs (values = original index), the batched segmented workload and
-more than 2^30 keys.
+uint64-key pairs (values = original index), the batched segmented workload,
+more than 2^30 keys and more than 2^31 keys (64-bit counts and positions).
 
-The oracle runs at full size in every case and every element is compared.
+Every element is compared, against the oracle run at full size, or, for the
+permutation inputs beyond 2^31 keys, against their closed-form sorted order.
 """
 import numpy as np
 import pytest
@@ -125,4 +126,82 @@ def test_full_keys_beyond_2p30(ow):
     del out
     torch.cuda.empty_cache()
     want = oracle.sort(keys)[0]
+    assert np.array_equal(got, want)
+
+
+N31 = (1 << 31) + 4097
+# key_i = (A * i + B) mod n is a permutation of 0 .. n - 1 (A is prime and
+# does not divide n), so the sorted keys are 0, 1, ..., n - 1 and the value
+# (input index) at sorted position k is A^-1 (k - B) mod n.
+PERM_A, PERM_B = 2654435761, 12345
+
+
+def _perm_keys(n):
+    import math
+    assert math.gcd(PERM_A, n) == 1
+    i = torch.arange(n, dtype=torch.int64, device="cuda")
+    k = (i * (PERM_A % n) + PERM_B) % n
+    del i
+    return k.to(torch.int32).view(torch.uint32)
+
+
+def _check_sorted_permutation(ko, vo, n, chunk=1 << 28):
+    ainv = pow(PERM_A, -1, n)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        k = torch.arange(lo, hi, dtype=torch.int64, device="cuda")
+        got = ko[lo:hi].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        assert torch.equal(got, k), f"keys differ in [{lo}, {hi})"
+        if vo is not None:
+            want = ((k - PERM_B) % n) * ainv % n
+            gotv = vo[lo:hi].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+            assert torch.equal(gotv, want), f"values differ in [{lo}, {hi})"
+
+
+def test_full_keys_beyond_2p31_permutation(ow):
+    """2^31 + 4097 uint32 keys (a permutation of 0 .. n - 1): 64-bit
+    histogram counts in portions of 2^30 keys, 64-bit bin starts carried
+    across five strips per pass, 64-bit positions; the output must be
+    0, 1, ..., n - 1."""
+    n = N31
+    print(f"[full] 2^31 + 4097 u32 keys (permutation), n={n}", flush=True)
+    keys = _perm_keys(n)
+    out = ow.sort_keys(keys)
+    del keys
+    torch.cuda.synchronize()
+    _check_sorted_permutation(out, None, n)
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_full_pairs_beyond_2p31_permutation(ow):
+    """2^31 + 4097 (uint32 key, uint32 value = input index) pairs, keys a
+    permutation: every value must be the input index of the key at its
+    position, A^-1 (k - B) mod n."""
+    n = N31
+    print(f"[full] 2^31 + 4097 u32 pairs (permutation), n={n}", flush=True)
+    keys = _perm_keys(n)
+    vals = torch.arange(n, dtype=torch.int64, device="cuda").to(torch.int32).view(torch.uint32)
+    ko, vo = ow.sort_pairs(keys, vals)
+    del keys, vals
+    torch.cuda.synchronize()
+    _check_sorted_permutation(ko, vo, n)
+    del ko, vo
+    torch.cuda.empty_cache()
+
+
+def test_full_keys_beyond_2p31_uniform(ow):
+    """2^31 + 4097 uniform uint32 keys against the oracle, element by
+    element."""
+    n = N31
+    print(f"[full] 2^31 + 4097 u32 keys (uniform), n={n}", flush=True)
+    keys = W.uniform(92, n)
+    d = torch.from_numpy(keys).cuda()
+    out = ow.sort_keys(d)
+    del d
+    got = out.cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    want = oracle.sort(keys)[0]
+    del keys
     assert np.array_equal(got, want)

@@ -132,6 +132,34 @@ def test_binning_pass_parity_and_final_status(ow, kb, vals, rank):
                 assert np.all(st[:, 1 << width:] == np.uint32(2 << 30))
 
 
+def test_lookback_wait_is_bounded(ow):
+    """The look-back wait is bounded: with a limit of one poll, a tile that does
+    not meet an inclusive prefix in its first window of predecessors gives up
+    and records the look-back error (word 1 of the binning pass's temporary
+    storage) instead of waiting; the pass still ends and every store stays in
+    bounds. With the default limit the same pass records no error and matches
+    the oracle."""
+    n = (1 << 24) + 4097
+    keys = W.uniform(77, n)
+    hist = oracle.histograms(keys, 0, 8, 8)[0]
+    off = oracle.exclusive_sums(hist[None, :])[0].astype(np.uint32)
+    want, _ = oracle.binning_pass(keys, 0, 8, off.astype(np.uint64))
+    d_keys, d_off = dev(keys), dev(off)
+    print("[lookback] default limit", flush=True)
+    dk, _, temp = ow.binning_pass(d_keys, d_off, 0, 8)
+    torch.cuda.synchronize()
+    assert int(host(temp[4:8].view(torch.uint32))[0]) == 0
+    assert np.array_equal(host(dk), want)
+    print("[lookback] limit of one poll", flush=True)
+    dk, _, temp = ow.binning_pass(d_keys, d_off, 0, 8,
+                                  config=ow.make_config(lookback_spin_limit=1))
+    torch.cuda.synchronize()
+    assert int(host(temp[4:8].view(torch.uint32))[0]) == 1
+    bad = ow.make_config(lookback_spin_limit=-1)
+    with pytest.raises(ow.OnesweepError):
+        ow.binning_pass(d_keys, d_off, 0, 8, config=bad)
+
+
 # ------------------------------------------------------------------ whole sorts
 
 def check_sort(ow, keys, vals, begin, end, cfg=None, inplace=False):

@@ -31,12 +31,17 @@ def test_glorot_params_match_the_layer_layout():
 
 
 def test_summary_regret_and_gain():
+    """gain = default / learned (selection included), regret = learned / best
+    - 1; inputs of 2^26 keys or more are summarised apart (selection runs
+    only there)."""
     from paper_2206_01784_amd import learned as L
-    rows = [dict(best_ms=1.0, default_ms=2.0, pick_ms=1.0, select_ms=0.0),
-            dict(best_ms=2.0, default_ms=2.0, pick_ms=3.0, select_ms=1.0)]
+    rows = [dict(n=1 << 20, best_ms=1.0, default_ms=2.0, learned_ms=1.0, pick_ms=1.0),
+            dict(n=1 << 27, best_ms=2.0, default_ms=2.0, learned_ms=4.0, pick_ms=3.0)]
     s = L.summarize(rows)
-    assert s["inputs"] == 2
+    assert s["inputs"] == 2 and s["inputs_selected"] == 1
     assert math.isclose(s["regret_mean"], (0.0 + 1.0) / 2)
     assert math.isclose(s["gain_geomean"], math.sqrt(2.0 * 0.5))
     assert math.isclose(s["gain_geomean_without_selection"], math.sqrt(2.0 * 2.0 / 3.0))
     assert math.isclose(s["best_over_default_geomean"], math.sqrt(2.0))
+    assert math.isclose(s["gain_geomean_selected"], 0.5)
+    assert math.isclose(s["best_over_default_geomean_selected"], 1.0)
