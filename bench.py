@@ -123,8 +123,9 @@ def summarize_counters(fetch_csv, write_csv, workload="u32_keys_uniform"):
             raise SystemExit(f"no dispatches of {pattern} in the counter file")
         return vals
 
-    # the chained-scan binning kernel: template mode argument 0
-    binning = r"binning_kernel<[^<>]*, 0, (false|true)>"
+    # the chained-scan binning kernel: template mode argument 0 (then the key
+    # order flag and the element position type)
+    binning = r"binning_kernel<[^<>]*, 0, (false|true), unsigned (int|long)>"
     copy_f = max(pick(fetch, "copy_kernel")) * 1024
     copy_w = max(pick(write, "copy_kernel")) * 1024
     bin_f = st.mean(pick(fetch, binning)) * 1024
@@ -138,12 +139,12 @@ def summarize_counters(fetch_csv, write_csv, workload="u32_keys_uniform"):
         f"# fetch csv: {os.path.basename(fetch_csv)}; write csv: {os.path.basename(write_csv)}",
         "# scale = bytes the plain copy kernel must move / its counter reading",
         "# commands (repo root; run from /tmp with TMPDIR=/tmp):",
-        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- "
-        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-cpu-baseline "
-        "--no-rts-baseline --calibrate-copy",
-        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o write -- "
-        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-cpu-baseline "
-        "--no-rts-baseline --calibrate-copy",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o pmc -- "
+        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-rts-baseline "
+        "--no-cpu-baseline --no-segments --calibrate-copy",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o pmc -- "
+        f"python bench.py --workload {workload} --steps 2 --warmup 0 --no-rts-baseline "
+        "--no-cpu-baseline --no-segments --calibrate-copy",
         "#   python bench.py --workload " + workload + " --counters-summary <fetch csv> <write csv>",
         f"kernel_source_sha256_16: {kernel_source_hash()}",
         f"workload: {workload}",
