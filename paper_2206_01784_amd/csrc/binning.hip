@@ -21,6 +21,8 @@
 //   5. keys are regrouped by digit in LDS and written out as runs at
 //      global bin offset + bin-relative tile offset + position in the run;
 //      values follow with the same destinations.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -28,8 +30,10 @@ namespace onesweep {
 
 // Two ways to find, for every lane of a wavefront, the lanes holding the
 // same digit (its "peers"), which is all the multi-split needs:
-//  - kRankBallot: one ballot per digit bit; a lane ANDs each ballot or its
-//    complement, by the value of its own bit (the paper's description);
+//  - kRankBallot: one ballot per digit bit (the paper's match). A lane ORs
+//    together each ballot XOR its own bit, which leaves the lanes holding
+//    another digit; its peers are the other lanes. On gfx950 the OR-of-XOR
+//    is one three-input bit operation per 32-lane half;
 //  - kRankPresence: every lane ORs its lane bit into a 64-bit presence mask
 //    per digit in LDS and reads the mask back. OR is order-independent, so
 //    the mask is exact whatever order the LDS serves the lanes in, and it
@@ -206,115 +210,130 @@ __global__ void __launch_bounds__(kBlock)
   // 1. Load. For ranking, a lane past the end of a ragged tile holds the key
   // whose ordered bits are all ones: its digit is the largest the place can
   // hold and it ranks after every real key, so the padding occupies the last
-  // tile positions, which are never written out. Keys-only tiles load
-  // unconditionally (such lanes load the tile's last key, in bounds, and
-  // take the padding only when ranked), so no branch separates the loads
-  // from the ranking and each batch waits only for its own load; pairs load
-  // in two branches, which needs fewer registers where their values are live.
+  // tile positions, which are never written out. Loading and ranking are
+  // compiled twice: for a full tile (no bounds checks: one address and
+  // immediate offsets) and for a ragged one. In a ragged keys-only tile the
+  // loads are unconditional (lanes past the end load the tile's last key,
+  // in bounds, and take the padding only when ranked), so no branch
+  // separates the loads from the ranking and each batch waits only for its
+  // own load; pairs load in two branches, which needs fewer registers where
+  // their values are live.
   K key[kIpt];
   const Idx wave_base = tile_base + static_cast<uint32_t>(wave * kWaveItems + lane);
   const K pad = kOrdered ? static_cast<K>(a.order.pad) : static_cast<K>(~K(0));
-  if constexpr (kVals) {
-    if (full) {
+  PackedPos<kIpt> pos;
+  const uint32_t wave_table = static_cast<uint32_t>(wave) * kRadix * kEntryWords;
+  auto load_and_rank = [&](auto full_tag) {
+    constexpr bool kFull = decltype(full_tag)::value;
+    if constexpr (kFull) {
 #pragma unroll
       for (int i = 0; i < kIpt; ++i) key[i] = src[wave_base + static_cast<uint32_t>(i * kWave)];
-    } else {
+    } else if constexpr (kVals) {
 #pragma unroll
       for (int i = 0; i < kIpt; ++i) {
         const Idx idx = wave_base + static_cast<uint32_t>(i * kWave);
         key[i] = idx < tile_end ? src[idx] : pad;
       }
-    }
-  } else {
+    } else {
 #pragma unroll
-    for (int i = 0; i < kIpt; ++i) {
-      const Idx idx = wave_base + static_cast<uint32_t>(i * kWave);
-      key[i] = src[full || idx < tile_end ? idx : tile_end - 1u];
+      for (int i = 0; i < kIpt; ++i) {
+        const Idx idx = wave_base + static_cast<uint32_t>(i * kWave);
+        key[i] = src[idx < tile_end ? idx : tile_end - 1u];
+      }
     }
-  }
-  if (tid < kRadix) s_gbase[tid] = bin_base + bin_start_load;
-  auto ranked = [&](int i) -> K {
-    return (full || wave_base + static_cast<uint32_t>(i * kWave) < tile_end) ? key[i] : pad;
+    if (tid < kRadix) s_gbase[tid] = bin_base + bin_start_load;
+    auto ranked = [&](int i) -> K {
+      if constexpr (kFull) return key[i];
+      else return wave_base + static_cast<uint32_t>(i * kWave) < tile_end ? key[i] : pad;
+    };
+    // 2. Wave64 multi-split ranking: pos[i] becomes the key's rank among the
+    // wave's earlier keys with the same digit.
+    if constexpr (kRank == kRankAtomic) {
+      // Batch i's previous count is read back kDepth batches later, so only
+      // kDepth (prior, leader) pairs are live at a time.
+      constexpr int kDepth = kIpt < 3 ? kIpt : 3;
+      uint32_t prior[kIpt], leader[kIpt];
+#pragma unroll
+      for (int i = 0; i < kIpt + kDepth; ++i) {
+        if (i >= kDepth) {
+          const int r = i - kDepth;
+          pos.add(r, __shfl(prior[r], static_cast<int>(leader[r]), kWave));
+        }
+        if (i >= kIpt) continue;
+        const uint32_t d = digit(ranked(i));
+        uint32_t peers_lo = ~0u, peers_hi = ~0u;
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+          const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);  // 0 or -1
+          const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
+          peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
+          peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+        pos.set(i, below);
+        leader[i] = peers_lo != 0u ? static_cast<uint32_t>(__builtin_ctz(peers_lo))
+                                   : 32u + static_cast<uint32_t>(__builtin_ctz(peers_hi));
+        prior[i] = 0u;
+        if (below == 0u)
+          prior[i] = atomicAdd(&s_rank[wave_table + d],
+                               static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi)));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kIpt; ++i) {
+        const uint32_t d = digit(ranked(i));
+        const uint32_t e = wave_table + d * kEntryWords;
+        // below: lanes under this one holding the same digit; group: all such
+        // lanes of the batch.
+        uint32_t below, group;
+        if constexpr (kRank == kRankPresence) {
+          uint64_t *presence = reinterpret_cast<uint64_t *>(s_rank + e + 2);
+          __hip_atomic_fetch_or(presence, 1ull << lane, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WORKGROUP);
+          __builtin_amdgcn_wave_barrier();
+          const uint32_t peers_lo = s_rank[e + 2];
+          const uint32_t peers_hi = s_rank[e + 3];
+          below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+          group = static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi));
+        } else {
+          // The lanes whose digit differs from this lane's: per bit, the vote
+          // XOR this lane's bit (all ones or zero), ORed in, one three-input
+          // operation per 32-lane half (a | (b ^ c) is truth table 0xF6).
+          uint32_t mis_lo = 0u, mis_hi = 0u;
+#pragma unroll
+          for (int b = 0; b < kRadixBits; ++b) {
+            // Bits at or above the place width are 0 in every lane: the vote is
+            // empty and adds nothing.
+            uint32_t own = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(d), b, 1));
+            asm volatile("" : "+v"(own));  // vote on the extracted bit: one compare
+            const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0u);
+            mis_lo = __builtin_amdgcn_bitop3_b32(mis_lo, static_cast<uint32_t>(vote), own, 0xF6);
+            mis_hi = __builtin_amdgcn_bitop3_b32(mis_hi, static_cast<uint32_t>(vote >> 32), own, 0xF6);
+          }
+          below = static_cast<uint32_t>(lane) -
+                  __builtin_amdgcn_mbcnt_hi(mis_hi, __builtin_amdgcn_mbcnt_lo(mis_lo, 0u));
+          group = static_cast<uint32_t>(kWave - __popc(mis_lo) - __popc(mis_hi));
+        }
+        const uint32_t prior = s_rank[e];
+        // Count the peers below this lane now: left to the scheduler, the count
+        // sinks to after the last batch and keeps every batch's two lane masks
+        // live, which spills keys to scratch memory.
+        asm volatile("" : "+v"(below));
+        pos.set(i, prior + below);
+        // Every lane of the group stores the same new count (and clears the
+        // presence mask), so the result does not depend on which store lands.
+        const uint32_t next = prior + group;
+        if constexpr (kRank == kRankPresence) {
+          *reinterpret_cast<uint4 *>(s_rank + e) = make_uint4(next, 0u, 0u, 0u);
+        } else {
+          s_rank[e] = next;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
   };
-
-  // 2. Wave64 multi-split ranking: pos[i] becomes the key's rank among the
-  // wave's earlier keys with the same digit.
-  PackedPos<kIpt> pos;
-  const uint32_t wave_table = static_cast<uint32_t>(wave) * kRadix * kEntryWords;
-  if constexpr (kRank == kRankAtomic) {
-    // Batch i's previous count is read back kDepth batches later, so only
-    // kDepth (prior, leader) pairs are live at a time.
-    constexpr int kDepth = kIpt < 3 ? kIpt : 3;
-    uint32_t prior[kIpt], leader[kIpt];
-#pragma unroll
-    for (int i = 0; i < kIpt + kDepth; ++i) {
-      if (i >= kDepth) {
-        const int r = i - kDepth;
-        pos.add(r, __shfl(prior[r], static_cast<int>(leader[r]), kWave));
-      }
-      if (i >= kIpt) continue;
-      const uint32_t d = digit(ranked(i));
-      uint32_t peers_lo = ~0u, peers_hi = ~0u;
-#pragma unroll
-      for (int b = 0; b < kRadixBits; ++b) {
-        const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);  // 0 or -1
-        const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
-        peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
-        peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
-      }
-      const uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
-      pos.set(i, below);
-      leader[i] = peers_lo != 0u ? static_cast<uint32_t>(__builtin_ctz(peers_lo))
-                                 : 32u + static_cast<uint32_t>(__builtin_ctz(peers_hi));
-      prior[i] = 0u;
-      if (below == 0u)
-        prior[i] = atomicAdd(&s_rank[wave_table + d],
-                             static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi)));
-    }
-  } else {
-#pragma unroll
-  for (int i = 0; i < kIpt; ++i) {
-    const uint32_t d = digit(ranked(i));
-    const uint32_t e = wave_table + d * kEntryWords;
-    uint32_t peers_lo, peers_hi;
-    if constexpr (kRank == kRankPresence) {
-      uint64_t *presence = reinterpret_cast<uint64_t *>(s_rank + e + 2);
-      __hip_atomic_fetch_or(presence, 1ull << lane, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_WORKGROUP);
-      __builtin_amdgcn_wave_barrier();
-      peers_lo = s_rank[e + 2];
-      peers_hi = s_rank[e + 3];
-    } else {
-      peers_lo = ~0u;
-      peers_hi = ~0u;
-#pragma unroll
-      for (int b = 0; b < kRadixBits; ++b) {
-        // Bits at or above the place width are 0 in every lane: the vote is
-        // empty and the mask is unchanged.
-        const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);  // 0 or -1
-        const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
-        peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
-        peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
-      }
-    }
-    const uint32_t prior = s_rank[e];
-    uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
-    // Count the peers below this lane now: left to the scheduler, the count
-    // sinks to after the last batch and keeps every batch's two peer masks
-    // live, which spills keys to scratch memory.
-    asm volatile("" : "+v"(below));
-    pos.set(i, prior + below);
-    // Every lane of the group stores the same new count (and clears the
-    // presence mask), so the result does not depend on which store lands.
-    const uint32_t next = prior + static_cast<uint32_t>(__popc(peers_lo) + __popc(peers_hi));
-    if constexpr (kRank == kRankPresence) {
-      *reinterpret_cast<uint4 *>(s_rank + e) = make_uint4(next, 0u, 0u, 0u);
-    } else {
-      s_rank[e] = next;
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  }
+  if (full) load_and_rank(std::true_type{});
+  else load_and_rank(std::false_type{});
   __syncthreads();
 
   // 3. Per-digit sums: over waves (each wave's start inside its digit run)
@@ -353,9 +372,16 @@ __global__ void __launch_bounds__(kBlock)
     for (int w = 0; w < kWaves; ++w) s_rank[(w * kRadix + tid) * kEntryWords] += local_start;
   }
   __syncthreads();
+  if (full) {
 #pragma unroll
-  for (int i = 0; i < kIpt; ++i)
-    pos.add(i, s_rank[wave_table + digit(ranked(i)) * kEntryWords]);
+    for (int i = 0; i < kIpt; ++i) pos.add(i, s_rank[wave_table + digit(key[i]) * kEntryWords]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+      const bool in = wave_base + static_cast<uint32_t>(i * kWave) < tile_end;
+      pos.add(i, s_rank[wave_table + digit(in ? key[i] : pad) * kEntryWords]);
+    }
+  }
   __syncthreads();  // the rank tables are dead; the region now holds the tile
   const uint32_t uniform = kShortCircuit ? s_uniform : 0u;
 
@@ -503,6 +529,16 @@ __global__ void __launch_bounds__(kBlock)
 // Instantiated shapes: (key type, values, workgroup size, items per thread,
 // rank algorithm).
 #define ONESWEEP_BINNING_SHAPES(X)    \
+  X(uint32_t, false, 1024, 16, 0)     \
+  X(uint32_t, false, 1024, 18, 0)     \
+  X(uint32_t, false, 1024, 19, 0)     \
+  X(uint32_t, false, 1024, 19, 1)     \
+  X(uint32_t, false, 1024, 19, 2)     \
+  X(uint32_t, true, 1024, 16, 0)      \
+  X(uint32_t, true, 1024, 18, 0)      \
+  X(uint32_t, true, 1024, 19, 0)      \
+  X(uint32_t, true, 1024, 18, 1)      \
+  X(uint32_t, true, 1024, 18, 2)      \
   X(uint32_t, false, 256, 8, 0)       \
   X(uint32_t, false, 256, 8, 1)       \
   X(uint32_t, true, 256, 8, 0)        \
@@ -608,6 +644,12 @@ __global__ void __launch_bounds__(kBlock)
 // Shapes built for the reduce-then-scan baseline (ballot ranking): the
 // default shapes of every key width and value presence.
 #define ONESWEEP_DOWNSWEEP_SHAPES(X) \
+  X(uint32_t, false, 1024, 16, 0)    \
+  X(uint32_t, true, 1024, 16, 0)     \
+  X(uint32_t, false, 1024, 18, 0)    \
+  X(uint32_t, false, 1024, 19, 0)    \
+  X(uint32_t, true, 1024, 18, 0)     \
+  X(uint32_t, true, 1024, 19, 0)     \
   X(uint32_t, false, 256, 8, 0)      \
   X(uint32_t, true, 256, 8, 0)       \
   X(uint32_t, false, 512, 16, 0)     \
@@ -627,8 +669,8 @@ __global__ void __launch_bounds__(kBlock)
 // Shapes built with 64-bit element positions for sorts of 2^31 elements or
 // more: the default large-input shape of each key width and value presence.
 #define ONESWEEP_WIDE_SHAPES(X)   \
-  X(uint32_t, false, 1024, 11, 0) \
-  X(uint32_t, true, 1024, 11, 0)  \
+  X(uint32_t, false, 1024, 19, 0) \
+  X(uint32_t, true, 1024, 18, 0)  \
   X(uint64_t, false, 1024, 9, 0)  \
   X(uint64_t, true, 1024, 8, 0)
 
@@ -659,23 +701,34 @@ size_t binning_tile_items(const BinningShape &s) {
 
 // The autotuned plain configuration: the fastest tile shape per key width,
 // value presence and input size, measured on MI355X over uniform inputs of
-// 2^18..2^28 keys (and the seeded sweep of 2^17..2^28). Small inputs want
-// more, smaller tiles to fill 256 CUs; from 2^21 keys on, the largest tile
-// that two 1024-thread workgroups per CU can hold wins: 32-bit keys and pairs
-// 1024 x 11 (2^28 keys: 3.24 against 3.63 ms with 1024 x 8; pairs 5.37
-// against 5.54 with 512 x 16), 64-bit keys 1024 x 9 (3% faster than
-// 1024 x 8); 64-bit pairs stay at 1024 x 8.
+// 2^18..2^28 keys. Small inputs want more, smaller tiles to fill 256 CUs;
+// larger ones the largest tile that two 1024-thread workgroups per CU hold
+// without spilling, since a larger tile spreads the look-back and the
+// workgroup's fixed work over more keys. 32-bit keys (ms per sort):
+// 1024 x 16 from 2^22 (0.107 against 0.119 with 1024 x 11), 1024 x 19
+// from 2^23 (2^28: 2.45 against 2.58 with 1024 x 16 and 2.95 with
+// 1024 x 11). 32-bit pairs: 1024 x 16 from 2^22 (2^26: 1.23 against 1.29
+// with 1024 x 11 and 1.27 with 1024 x 18), 1024 x 18 from 2^28 (4.84
+// against 4.96 with 1024 x 16; it spills a few registers, which costs more
+// than the larger tile saves below 2^28). 64-bit keys 1024 x 9 (3% faster
+// than 1024 x 8); 64-bit pairs stay at 1024 x 8.
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
-  const bool large = n >= (size_t(1) << 21);
   if (key_bits == 64) {
     if (has_values && n < (size_t(3) << 16)) return BinningShape{64, true, 256, 8, kRankBallot};
     if (n < (size_t(1) << 19)) return BinningShape{64, has_values, 512, 8, kRankBallot};
-    if (large && !has_values) return BinningShape{64, false, 1024, 9, kRankBallot};
+    if (n >= (size_t(1) << 21) && !has_values) return BinningShape{64, false, 1024, 9, kRankBallot};
     return BinningShape{64, has_values, 1024, 8, kRankBallot};
   }
   if (n < (size_t(1) << 18)) return BinningShape{32, has_values, 256, 8, kRankBallot};
-  if (large) return BinningShape{32, has_values, 1024, 11, kRankBallot};
-  return BinningShape{32, has_values, 1024, 8, kRankBallot};
+  if (n < (size_t(1) << 21)) return BinningShape{32, has_values, 1024, 8, kRankBallot};
+  if (has_values) {
+    if (n < (size_t(1) << 22)) return BinningShape{32, true, 1024, 8, kRankBallot};
+    if (n < (size_t(1) << 28)) return BinningShape{32, true, 1024, 16, kRankBallot};
+    return BinningShape{32, true, 1024, 18, kRankBallot};
+  }
+  if (n < (size_t(1) << 22)) return BinningShape{32, false, 1024, 11, kRankBallot};
+  if (n < (size_t(1) << 23)) return BinningShape{32, false, 1024, 16, kRankBallot};
+  return BinningShape{32, false, 1024, 19, kRankBallot};
 }
 
 // The default tile shape of the segmented sort's large segments, measured on

@@ -241,7 +241,9 @@ __global__ void __launch_bounds__(1024) select_kernel(SelectArgs a) {
     const int d = a.default_class;
     if (d >= 0 && ((a.class_mask >> d) & 1u) && !(s_out[best] < s_out[d] - a.margin)) best = d;
     *a.choice = best;
-    if (a.host_choice) *a.host_choice = best;
+    // The host may poll this word while the kernel is still running.
+    if (a.host_choice)
+      __hip_atomic_store(a.host_choice, best, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 

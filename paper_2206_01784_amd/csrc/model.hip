@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 #include "internal.hpp"
@@ -26,13 +27,14 @@ struct ModelClass {
 };
 
 // Classes of a freshly created model: the plain sort's tile shapes with
-// ballot ranking (the 1024-thread tiles of 9-11 keys per thread included),
-// and presence-mask ranking for the smallest and the 1024-thread tiles.
+// ballot ranking (every large-input default of 32-bit keys and pairs
+// included: 1024 x 11, 16, 18 and 19 keys per thread, each built for keys
+// and pairs) and presence-mask ranking for the smallest tiles.
 // (key-width mask 1 = 32-bit, 2 = 64-bit, 3 = both; rank 1 ballots, 2 masks.)
 constexpr ModelClass kDefaultClasses[kMlpClasses] = {
     {3, 256, 8, 1, 0},    {3, 256, 16, 1, 0},  {2, 512, 8, 1, 0},   {3, 512, 12, 1, 0},
-    {1, 512, 16, 1, 0},   {3, 1024, 8, 1, 0},  {1, 1024, 10, 1, 0}, {1, 1024, 11, 1, 0},
-    {2, 1024, 9, 1, 0},   {3, 256, 8, 2, 0},   {3, 1024, 8, 2, 0},  {1, 1024, 11, 2, 0}};
+    {1, 512, 16, 1, 0},   {3, 1024, 8, 1, 0},  {1, 1024, 11, 1, 0}, {1, 1024, 16, 1, 0},
+    {1, 1024, 18, 1, 0},  {1, 1024, 19, 1, 0}, {2, 1024, 9, 1, 0},  {3, 256, 8, 2, 0}};
 
 constexpr char kMagic[8] = {'O', 'S', 'W', 'M', 'L', 'P', '0', '1'};
 
@@ -254,6 +256,9 @@ constexpr size_t kLearnedMaxN = size_t(1) << 28;
 // A class replaces the autotuned default only when predicted faster by more
 // than this (log-time units, about 2%).
 constexpr float kSelectMargin = 0.02f;
+// The host-mapped choice word before the selection kernel writes it (the
+// kernel writes a class index or -1).
+constexpr int kChoicePending = -2;
 
 void class_fields(const ModelClass &c, onesweep_config_t *cfg) {
   cfg->block_threads = c.block_threads;
@@ -634,8 +639,19 @@ onesweep_status_t onesweep_sort_learned(const onesweep_model_t *m, void *d_temp,
   late.ctx = &ctx;
   late.choose = [](void *p, onesweep_config_t *c) -> onesweep_status_t {
     Ctx &x = *static_cast<Ctx *>(p);
-    hipError_t e = hipEventSynchronize(x.m->picked);
-    if (e != hipSuccess) return hip_fail(e, "selection event");
+    // The selection kernel stores its choice to mapped host memory as its
+    // last step: poll that word (microseconds) rather than wait on the event;
+    // after 20 ms fall back to the event.
+    const auto t0 = std::chrono::steady_clock::now();
+    while (__atomic_load_n(x.m->host_choice, __ATOMIC_ACQUIRE) == kChoicePending) {
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+        hipError_t e = hipEventSynchronize(x.m->picked);
+        if (e != hipSuccess) return hip_fail(e, "selection event");
+        if (__atomic_load_n(x.m->host_choice, __ATOMIC_ACQUIRE) == kChoicePending)
+          return fail(ONESWEEP_ERROR_HIP, "selection kernel wrote no choice");
+        break;
+      }
+    }
     onesweep_status_t st = chosen_class(x.m, c);
     x.picked = *c;
     return st;
@@ -652,7 +668,7 @@ onesweep_status_t onesweep_sort_learned(const onesweep_model_t *m, void *d_temp,
   // The selection kernel reads the keys on the model's stream, after what the
   // caller enqueued before, while the sort's clear, histogram and exclusive
   // sums run on the caller's stream.
-  *m->host_choice = -1;
+  __atomic_store_n(m->host_choice, kChoicePending, __ATOMIC_RELEASE);
   MLP_TRY(hipEventRecord(m->fork, s), "fork");
   MLP_TRY(hipStreamWaitEvent(m->aux, m->fork, 0), "fork");
   MLP_TRY(launch_select(key_bits, select_args(m, d_keys_in, n, key_bits, begin_bit, end_bit,

@@ -37,8 +37,8 @@ def test_counter_summary_scales_by_the_copy_and_keeps_chained_binning_only(tmp_p
     out = tmp_path / "traffic.txt"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
     n = 1 << 28
-    chained = "void onesweep::binning_kernel<unsigned int, false, 1024, 8, 0, 0, false>(x)"
-    downsweep = "void onesweep::binning_kernel<unsigned int, false, 1024, 8, 0, 2, false>(x)"
+    chained = "void onesweep::binning_kernel<unsigned int, false, 1024, 8, 0, 0, false, unsigned int>(x)"
+    downsweep = "void onesweep::binning_kernel<unsigned int, false, 1024, 8, 0, 2, false, unsigned int>(x)"
     copy = "onesweep::copy_kernel(onesweep::CopyArgs)"
     # FETCH_SIZE reads half the true bytes, WRITE_SIZE the true bytes (KiB)
     write_counters(tmp_path / "f.csv", [(copy, n * 4 / 2 / 1024), (chained, 600000.0),

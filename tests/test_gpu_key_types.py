@@ -19,8 +19,10 @@ DTYPES = {("unsigned", 32): np.uint32, ("unsigned", 64): np.uint64,
           ("signed", 32): np.int32, ("signed", 64): np.int64,
           ("float", 32): np.float32, ("float", 64): np.float64}
 SHAPES = {
-    (32, False): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11)],
-    (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11)],
+    (32, False): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11),
+                  (1024, 19)],
+    (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11),
+                 (1024, 18)],
     (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
     (64, True): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
 }

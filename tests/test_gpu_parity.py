@@ -92,8 +92,10 @@ def test_histogram_empty_and_unaligned(ow):
 # ------------------------------------------------------------------ phase 3 (one pass)
 
 SHAPES = {
-    (32, False): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11)],
-    (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11)],
+    (32, False): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11),
+                  (1024, 19)],
+    (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11),
+                 (1024, 18)],
     (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
     (64, True): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
 }
@@ -178,6 +180,45 @@ def check_sort(ow, keys, vals, begin, end, cfg=None, inplace=False):
     assert np.array_equal(got_k, wk)
     if vals is not None:
         assert np.array_equal(got_v, wv)
+
+
+# Tile shapes built with ballot ranking only: the large-input defaults of the
+# other value presence (32-bit keys 1024 x 16 and 1024 x 18, pairs 1024 x 16
+# and 1024 x 19), so that every learned-selector class serves keys and pairs.
+BALLOT_ONLY_SHAPES = {False: [(1024, 16), (1024, 18)], True: [(1024, 16), (1024, 19)]}
+
+
+@pytest.mark.parametrize("vals", [False, True])
+def test_ballot_only_shapes(ow, vals):
+    for block, ipt in BALLOT_ONLY_SHAPES[vals]:
+        cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=1)
+        T = ow.tile_items(32, vals, cfg)
+        assert T == block * ipt
+        for n in (2, T - 1, T + 1, 7 * T + 333):
+            keys = W.uniform(17 + n % 13, n, 32)
+            v = np.arange(n, dtype=np.uint32) if vals else None
+            check_sort(ow, keys, v, 0, 32, cfg)
+        n = 5 * T + 77
+        keys = W.uniform(23, n, 32)
+        v = np.arange(n, dtype=np.uint32) if vals else None
+        for shift, width in ((0, 8), (24, 8), (5, 3)):
+            off = oracle.exclusive_sums(oracle.histograms(keys, shift, shift + width, width))[0]
+            off256 = np.full(256, n, dtype=np.uint32)
+            off256[:off.size] = off
+            dk, dv, _ = ow.binning_pass(dev(keys), dev(off256), shift, width,
+                                        src_values=None if v is None else dev(v), config=cfg)
+            wk, wv = oracle.binning_pass(keys, shift, width, off, v)
+            assert np.array_equal(host(dk), wk), (block, ipt, shift, width)
+            if vals:
+                assert np.array_equal(host(dv), wv), (block, ipt, shift, width)
+        # the other ranking methods are not built for these shapes: refused
+        for rank in (2, 3):
+            bad = ow.make_config(block, ipt, rank_algorithm=rank)
+            with pytest.raises(ow.OnesweepError):
+                if vals:
+                    ow.sort_pairs(dev(keys), dev(v), config=bad)
+                else:
+                    ow.sort_keys(dev(keys), config=bad)
 
 
 @pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
@@ -329,7 +370,7 @@ def test_graph_capture_replays(ow):
 # ------------------------------------------------------------------ reduce-then-scan baseline
 
 RTS_SHAPES = {
-    32: [(256, 8), (512, 16), (1024, 8), (1024, 11)],
+    32: [(256, 8), (512, 16), (1024, 8), (1024, 11), (1024, 16), (1024, 18), (1024, 19)],
     64: [(256, 8), (512, 8), (1024, 8)],
 }
 
