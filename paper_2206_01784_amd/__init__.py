@@ -455,7 +455,7 @@ class Model:
             _check(_lib.onesweep_model_load(os.fsencode(path), max_batch, ctypes.byref(self._h)))
         self.max_batch = max_batch
 
-    def __del__(self):
+    def __del__(self, _lib=_lib):  # the library bound here: module globals are gone at exit
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             _lib.onesweep_model_free(h)

@@ -539,7 +539,8 @@ onesweep_status_t segment_limits(const onesweep_config_t *cfg, uint32_t limit[kS
 struct SegmentLayout {
   uint32_t capacity[kSegClasses];
   uint32_t max_large, max_tiles;
-  size_t plan, counters, lists[kSegClasses], tile_info, hist, status, tmp_keys, tmp_vals, total;
+  size_t plan, counters, lists[kSegClasses], tile_info, large_len, hist, status, tmp_keys,
+      tmp_vals, total;
   size_t status_words_per_place;
 };
 
@@ -568,6 +569,8 @@ SegmentLayout segment_layout(size_t n, size_t num_segments, int key_bits, bool h
   }
   L.tile_info = off;
   off += align_up(sizeof(uint4) * L.max_tiles);
+  L.large_len = off;
+  off += align_up(sizeof(uint32_t) * L.max_large);
   L.hist = off;
   off += align_up(sizeof(uint32_t) * kRadix * places * static_cast<size_t>(L.max_large));
   L.status = off;
@@ -732,6 +735,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   SegmentPlan *plan = reinterpret_cast<SegmentPlan *>(temp + L.plan);
   uint32_t *counters = reinterpret_cast<uint32_t *>(temp + L.counters);
   uint4 *tile_info = reinterpret_cast<uint4 *>(temp + L.tile_info);
+  uint32_t *large_len = reinterpret_cast<uint32_t *>(temp + L.large_len);
   uint32_t *hist = reinterpret_cast<uint32_t *>(temp + L.hist);
   uint32_t *status = reinterpret_cast<uint32_t *>(temp + L.status);
 
@@ -748,6 +752,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   ca.max_tiles = L.max_tiles;
   ca.tile_items = static_cast<uint32_t>(tile);
   ca.tile_info = tile_info;
+  ca.large_len = large_len;
   ca.tile_counters = counters;
   ca.plan = plan;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_CLASSIFY, "classify", launch_classify(ca, stream));
@@ -805,23 +810,6 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   za.places = places;
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "segment clear",
                   launch_segment_clear(za, stream_grid, stream));
-  SegmentHistArgs ha{};
-  ha.keys = keys_in;
-  ha.tile_info = tile_info;
-  ha.hist = hist;
-  ha.plan = plan;
-  ha.begin_bit = begin_bit;
-  ha.end_bit = end_bit;
-  ha.places = places;
-  ha.order = rc.order;
-  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "segment histogram",
-                  launch_segment_histogram(key_bits, ha, std::min(L.max_tiles, stream_grid),
-                                           stream));
-  const uint32_t rows = L.max_large * static_cast<uint32_t>(places);
-  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_SCAN, "segment scan",
-                  launch_segment_scan(hist, plan, places,
-                                      std::min((rows + 3u) / 4u, stream_grid), stream));
-
   // Static routing of the large segments' passes: with the input aliasing
   // the output the first pass must not write the output, so the passes go
   // in -> tmp -> out -> tmp ... and an odd count ends with a copy; otherwise
@@ -834,12 +822,20 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
     if (alias) return (passes_done & 1) ? kBufTmp : kBufOut;
     return ((places - passes_done) & 1) ? kBufTmp : kBufOut;
   };
+  // The first place's launch also counts the digits of every place per
+  // segment (its first workgroups), so no separate histogram or scan launch
+  // precedes it; each tile turns its segment's counts into bin starts.
   SegmentTiles seg{};
   seg.tile_info = tile_info;
-  seg.bin_offsets = hist;
+  seg.counts = hist;
+  seg.large_len = large_len;
   seg.plan = plan;
   seg.places = places;
+  seg.begin_bit = begin_bit;
+  seg.end_bit = end_bit;
   for (int j = 0; j < places; ++j) {
+    const int mode = j == 0 ? kBinSegCounted : kBinSegmented;
+    const uint32_t grid = (j == 0 ? 2u : 1u) * L.max_tiles;
     const int lo = begin_bit + j * kRadixBits;
     const int width = (lo + kRadixBits <= end_bit) ? kRadixBits : end_bit - lo;
     const int from = buffer_after(j), to = buffer_after(j + 1);
@@ -860,7 +856,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
       a.shift = lo;
       a.width = width;
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "segment binning",
-                      launch_binning(rc.shape, kBinSegmented, &a, L.max_tiles, stream));
+                      launch_binning(rc.shape, mode, &a, grid, stream));
     } else {
       BinningArgs<uint64_t> a{};
       a.keys[kBufIn] = static_cast<uint64_t *>(kbuf[from]);
@@ -878,7 +874,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
       a.shift = lo;
       a.width = width;
       ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_BINNING, "segment binning",
-                      launch_binning(rc.shape, kBinSegmented, &a, L.max_tiles, stream));
+                      launch_binning(rc.shape, mode, &a, grid, stream));
     }
   }
   if (buffer_after(places) != kBufOut) {

@@ -82,6 +82,61 @@ struct PackedPos {
   }
 };
 
+// Digit counts of one tile of a large segment, for every place at once, added
+// to the segment's count rows with device-scope atomics (the counting half
+// of a kBinSegCounted launch). kCopies interleaved LDS copies per counter, as
+// in the upfront histogram.
+constexpr int kSegCountCopies = 4;
+
+template <typename K, bool kOrdered, int kBlock>
+__device__ void count_segment_tile(const K *__restrict__ keys, const uint4 info,
+                                   const SegmentTiles &seg, const KeyOrder &order,
+                                   uint32_t *s_hist) {
+  constexpr int kMaxP = static_cast<int>(sizeof(K));
+  constexpr int kBatch = 8;  // independent loads in flight per thread
+  const int tid = threadIdx.x;
+  const int places = seg.places;
+  int shifts[kMaxP];
+  uint32_t masks[kMaxP];
+#pragma unroll
+  for (int j = 0; j < kMaxP; ++j) {
+    const int lo = seg.begin_bit + j * kRadixBits;
+    const int hi = lo + kRadixBits < seg.end_bit ? lo + kRadixBits : seg.end_bit;
+    shifts[j] = j < places ? lo : 0;
+    masks[j] = j < places ? ((1u << (hi - lo)) - 1u) : 0u;
+  }
+  for (int i = tid; i < places * kRadix * kSegCountCopies; i += kBlock) s_hist[i] = 0u;
+  __syncthreads();
+  uint32_t *my_hist = s_hist + (tid % kSegCountCopies);
+  for (uint32_t base = 0; base < info.y; base += kBlock * kBatch) {
+    K k[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const uint32_t i = base + b * kBlock + tid;
+      k[b] = i < info.y ? keys[info.x + i] : K(0);
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (base + b * kBlock + tid >= info.y) continue;
+      const K o = kOrdered ? ordered_bits(k[b], order) : k[b];
+#pragma unroll
+      for (int j = 0; j < kMaxP; ++j)
+        if (j < places)
+          atomicAdd(&my_hist[(j * kRadix + (static_cast<uint32_t>(o >> shifts[j]) & masks[j])) *
+                             kSegCountCopies],
+                    1u);
+    }
+  }
+  __syncthreads();
+  uint32_t *dst = seg.counts + static_cast<size_t>(info.w) * places * kRadix;
+  for (int i = tid; i < places * kRadix; i += kBlock) {
+    uint32_t c = 0u;
+#pragma unroll
+    for (int k = 0; k < kSegCountCopies; ++k) c += s_hist[i * kSegCountCopies + k];
+    if (c != 0u) atomicAdd(&dst[i], c);
+  }
+}
+
 // Occupancy target (waves per SIMD the register allocation must allow).
 // 1024-thread workgroups always take 8 (64 registers): two of them per CU
 // keep twice the keys in flight of one, which outweighs a few spilled
@@ -95,9 +150,12 @@ constexpr int binning_waves_per_eu() {
 
 // kMode: kBinChained, one sequence with a chained scan over its tiles;
 // kBinSegmented, the tiles of the large segments of a segmented sort (each
-// segment its own chained scan and bin offsets); kBinDownsweep, the scatter
-// step of reduce-then-scan: every tile's exclusive prefix per digit is read
-// from a table that the upsweep and tile-scan kernels filled beforehand.
+// segment its own chained scan; a tile turns its segment's digit counts of
+// the place into bin starts itself); kBinSegCounted, the first place of the
+// segmented sort in the same launch as the counting of every place (see
+// count_segment_tile); kBinDownsweep, the scatter step of reduce-then-scan:
+// every tile's exclusive prefix per digit is read from a table that the
+// upsweep and tile-scan kernels filled beforehand.
 // kOrdered: keys are ranked by their ordered bits (signed, floating-point or
 // descending order); false for unsigned ascending sorts. Idx: type of element
 // positions (uint64_t for sorts of 2^31 elements or more).
@@ -106,7 +164,8 @@ template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode, bo
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(binning_waves_per_eu<K, kBlock, kIpt>())))
     binning_kernel(BinningArgs<K, Idx> a) {
-  constexpr bool kSeg = kMode == kBinSegmented;
+  constexpr bool kCounted = kMode == kBinSegCounted;
+  constexpr bool kSeg = kMode == kBinSegmented || kCounted;
   constexpr bool kRts = kMode == kBinDownsweep;
   constexpr int kWaves = kBlock / kWave;
   constexpr int kTile = kBlock * kIpt;
@@ -136,12 +195,16 @@ __global__ void __launch_bounds__(kBlock)
   constexpr bool kShortCircuit = sizeof(K) == 4 && kVals;
   constexpr size_t kKeyBytes = sizeof(K) * kTile;
   constexpr size_t kRankBytes = sizeof(uint32_t) * kWaves * kRadix * kEntryWords;
-  constexpr size_t kStageBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
+  constexpr size_t kTileBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
+  constexpr size_t kCountBytes =
+      kCounted ? sizeof(uint32_t) * sizeof(K) * kRadix * kSegCountCopies : 0;
+  constexpr size_t kStageBytes = kTileBytes > kCountBytes ? kTileBytes : kCountBytes;
   __shared__ __attribute__((aligned(16))) unsigned char s_stage[kStageBytes];
   __shared__ Idx s_gbase[kRadix];
   __shared__ uint32_t s_wave_sum[kRadix / kWave];
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_uniform;  // 1 + the tile's only digit, or 0
+  __shared__ uint32_t s_seg_sum[kRadix / kWave];  // segmented: digit counts per wave
 
   uint32_t *s_rank = reinterpret_cast<uint32_t *>(s_stage);
   K *s_keys = reinterpret_cast<K *>(s_stage);
@@ -161,9 +224,11 @@ __global__ void __launch_bounds__(kBlock)
 
   // The segmented grid is sized for the most tiles the offsets could need;
   // workgroups beyond the actual count leave before taking a tile id, so the
-  // ids handed out are exactly 0 .. tiles - 1.
+  // ids handed out are exactly 0 .. tiles - 1 (twice that in a counted
+  // launch: first the counting of every tile, then the binning of every tile).
   if constexpr (kSeg) {
-    if (a.seg.plan->error || blockIdx.x >= a.seg.plan->large_tiles) return;
+    const uint32_t items = (kCounted ? 2u : 1u) * a.seg.plan->large_tiles;
+    if (a.seg.plan->error || blockIdx.x >= items) return;
   }
   {
     uint4 *z = reinterpret_cast<uint4 *>(s_rank);
@@ -179,33 +244,93 @@ __global__ void __launch_bounds__(kBlock)
     s_uniform = 0u;
   }
   __syncthreads();
-  const uint32_t tile = s_tile + a.tile_first;  // tickets count from the strip's start
+  uint32_t tile = s_tile + a.tile_first;  // tickets count from the strip's start
+  if constexpr (kCounted) {
+    // Tickets below the tile count are counting work. Every binning tile's
+    // ticket is larger than every counting ticket, so a binning tile only
+    // waits on counting that workgroups already running have taken on.
+    const uint32_t large_tiles = a.seg.plan->large_tiles;
+    if (tile < large_tiles) {
+      count_segment_tile<K, kOrdered, kBlock>(src, a.seg.tile_info[tile], a.seg, a.order,
+                                              reinterpret_cast<uint32_t *>(s_stage));
+      return;
+    }
+    tile -= large_tiles;
+  }
   Idx tile_base, bin_base;
   uint32_t tile_count;
-  const Idx *bin_offsets;
   bool first;
+  uint4 seg_info = make_uint4(0u, 0u, 0u, 0u);
   if constexpr (kSeg) {
-    const uint4 info = a.seg.tile_info[tile];
-    tile_base = info.x;
-    tile_count = info.y;
-    bin_base = info.z;
-    first = info.x == info.z;
-    bin_offsets = a.seg.bin_offsets + (static_cast<size_t>(info.w) * a.seg.places + a.place) * kRadix;
+    seg_info = a.seg.tile_info[tile];
+    tile_base = seg_info.x;
+    tile_count = seg_info.y;
+    bin_base = seg_info.z;
+    first = seg_info.x == seg_info.z;
   } else {
     tile_base = static_cast<Idx>(tile) * static_cast<Idx>(kTile);
     const Idx left = n - tile_base;
     tile_count = left < static_cast<Idx>(kTile) ? static_cast<uint32_t>(left) : kTile;
     bin_base = 0u;
     first = tile == a.tile_first;
-    bin_offsets = a.bin_offsets;
   }
   const Idx tile_end = tile_base + tile_count;
   const bool full = tile_count == static_cast<uint32_t>(kTile);
 
   // The bin starts of this place, loaded before the keys so that waiting for
   // them does not wait for the keys; kept in s_gbase until the look-back.
+  // A segment's tile derives them from the segment's digit counts: each of
+  // threads 0..255 holds its digit's exclusive sum within its wave here and
+  // adds the lower waves' totals (s_seg_sum) at the look-back.
   Idx bin_start_load = 0u;
-  if (tid < kRadix) bin_start_load = bin_offsets[tid];
+  if constexpr (kSeg) {
+    const uint32_t *counts =
+        a.seg.counts + (static_cast<size_t>(seg_info.w) * a.seg.places + a.place) * kRadix;
+    uint32_t c = 0u;
+    if constexpr (kCounted) {
+      // Counting runs in this launch. The counts only grow and their final
+      // values add up to the segment's length, so a read of all 256 that
+      // adds up to the length has read every final value: no ordering
+      // between the counters is needed, only each counter's own.
+      const uint32_t len = a.seg.large_len[seg_info.w];
+      uint32_t rounds = 0u;
+      while (true) {
+        if (tid < kRadix)
+          c = __hip_atomic_load(const_cast<uint32_t *>(counts + tid), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t sum = tid < kRadix ? c : 0u;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+        if (tid < kRadix && lane == 0) s_seg_sum[wave] = sum;
+        __syncthreads();
+        uint32_t total = 0u;
+#pragma unroll
+        for (int w = 0; w < kRadix / kWave; ++w) total += s_seg_sum[w];
+        __syncthreads();
+        if (total == len) break;
+        if (++rounds >= a.spin_limit) {  // bounded wait: give up, record it
+          if (tid == 0)
+            __hip_atomic_store(a.lookback_error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    } else if (tid < kRadix) {
+      c = counts[tid];
+    }
+    if (tid < kRadix) {
+      uint32_t incl = c;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += t;
+      }
+      if (lane == kWave - 1) s_seg_sum[wave] = incl;
+      bin_start_load = incl - c;
+    }
+  } else if (tid < kRadix) {
+    bin_start_load = a.bin_offsets[tid];
+  }
 
   // 1. Load. For ranking, a lane past the end of a ragged tile holds the key
   // whose ordered bits are all ones: its digit is the largest the place can
@@ -407,7 +532,9 @@ __global__ void __launch_bounds__(kBlock)
   // trip reads a window of kLookback predecessors at once; tiles before the
   // first one read as an inclusive prefix of zero.
   if (tid < kRadix) {
-    const Idx bin_start = s_gbase[tid];
+    Idx bin_start = s_gbase[tid];
+    if constexpr (kSeg)
+      for (int w = 0; w < wave; ++w) bin_start += s_seg_sum[w];
     uint32_t exclusive = 0u;
     if constexpr (kRts) {
       // digit-major table of exclusive prefixes over tiles
@@ -684,7 +811,7 @@ bool binning_shape_supported(const BinningShape &s, int mode, bool wide) {
     if (mode == kBinChained) {
       ONESWEEP_WIDE_SHAPES(ONESWEEP_MATCH)
     }
-  } else if (mode == kBinSegmented) {
+  } else if (mode == kBinSegmented || mode == kBinSegCounted) {
     ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_MATCH)
   } else if (mode == kBinDownsweep) {
     ONESWEEP_DOWNSWEEP_SHAPES(ONESWEEP_MATCH)
@@ -761,6 +888,7 @@ hipError_t launch_binning(const BinningShape &s, int mode, const void *args, uin
 #define ONESWEEP_LAUNCH(K, V, B, I, R, MODE) ONESWEEP_LAUNCH_IDX(K, V, B, I, R, MODE, uint32_t)
 #define ONESWEEP_LAUNCH_FLAT(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinChained)
 #define ONESWEEP_LAUNCH_SEG(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinSegmented)
+#define ONESWEEP_LAUNCH_SEGC(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinSegCounted)
 #define ONESWEEP_LAUNCH_DOWN(K, V, B, I, R) ONESWEEP_LAUNCH(K, V, B, I, R, kBinDownsweep)
 #define ONESWEEP_LAUNCH_WIDE(K, V, B, I, R) \
   ONESWEEP_LAUNCH_IDX(K, V, B, I, R, kBinChained, uint64_t)
@@ -770,6 +898,8 @@ hipError_t launch_binning(const BinningShape &s, int mode, const void *args, uin
     }
   } else if (mode == kBinSegmented) {
     ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_LAUNCH_SEG)
+  } else if (mode == kBinSegCounted) {
+    ONESWEEP_SEGMENT_BINNING_SHAPES(ONESWEEP_LAUNCH_SEGC)
   } else if (mode == kBinDownsweep) {
     ONESWEEP_DOWNSWEEP_SHAPES(ONESWEEP_LAUNCH_DOWN)
   } else {
@@ -777,6 +907,7 @@ hipError_t launch_binning(const BinningShape &s, int mode, const void *args, uin
   }
 #undef ONESWEEP_LAUNCH_WIDE
 #undef ONESWEEP_LAUNCH_DOWN
+#undef ONESWEEP_LAUNCH_SEGC
 #undef ONESWEEP_LAUNCH_SEG
 #undef ONESWEEP_LAUNCH_FLAT
 #undef ONESWEEP_LAUNCH

@@ -77,9 +77,11 @@ static_assert(sizeof(SegmentPlan) == 256, "one 256-byte slot");
 // A tile with x == z starts its segment's chained scan.
 struct SegmentTiles {
   const uint4 *tile_info;       // [tiles]
-  const uint32_t *bin_offsets;  // [large][places][256] exclusive sums within the segment
+  uint32_t *counts;             // [large][places][256] digit counts within the segment
+  const uint32_t *large_len;    // [large] keys per large segment
   const SegmentPlan *plan;
   int places;
+  int begin_bit, end_bit;       // bit range of all places (the counting workgroups)
 };
 
 // Idx is the type of element positions: uint32_t below 2^31 elements,

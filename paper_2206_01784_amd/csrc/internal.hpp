@@ -49,7 +49,7 @@ onesweep_status_t sort_late_choice(void *d_temp, size_t *temp_bytes, const void 
 // sequence; the same per large segment of a segmented sort
 // (BinningArgs::seg); or the scatter (downsweep) step of the reduce-then-scan
 // baseline. Fewer shapes are built for the last two.
-enum BinningMode : int { kBinChained = 0, kBinSegmented = 1, kBinDownsweep = 2 };
+enum BinningMode : int { kBinChained = 0, kBinSegmented = 1, kBinDownsweep = 2, kBinSegCounted = 3 };
 
 // `wide`: 64-bit element positions (sorts of 2^31 elements or more), built
 // for the default large-input shapes of the chained mode only.
@@ -131,6 +131,7 @@ struct ClassifyArgs {
   uint32_t max_tiles;
   uint32_t tile_items;             // binning tile of the large segments
   uint4 *tile_info;                // [max_tiles]
+  uint32_t *large_len;             // [max_large] keys per large segment
   uint32_t *tile_counters;         // kMaxPlaces words, cleared
   SegmentPlan *plan;
 };
@@ -144,21 +145,6 @@ struct SegmentClearArgs {
   int places;
 };
 hipError_t launch_segment_clear(const SegmentClearArgs &a, uint32_t grid, hipStream_t stream);
-
-struct SegmentHistArgs {
-  const void *keys;
-  const uint4 *tile_info;
-  uint32_t *hist;  // [large][places][256]
-  const SegmentPlan *plan;
-  int begin_bit;
-  int end_bit;
-  int places;
-  KeyOrder order;
-};
-hipError_t launch_segment_histogram(int key_bits, const SegmentHistArgs &a, uint32_t grid,
-                                    hipStream_t stream);
-hipError_t launch_segment_scan(uint32_t *hist, const SegmentPlan *plan, int places, uint32_t grid,
-                               hipStream_t stream);
 
 struct SegmentCopyArgs {
   const void *keys_src;

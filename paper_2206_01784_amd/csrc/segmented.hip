@@ -11,10 +11,12 @@
 //  - LDS sort: one workgroup per segment loads it once, runs the LSD passes
 //    over 8-bit digits in LDS with the same wave64 multi-split ranking as the
 //    binning kernel, and writes it once.
-//  - large segments: an Onesweep sort per segment (Section 3): histograms of
-//    every place per segment, their exclusive sums, and one binning launch per
-//    place over the tiles of all large segments, each segment its own chained
-//    scan.
+//  - large segments: an Onesweep sort per segment (Section 3), one binning
+//    launch per place over the tiles of all large segments, each segment its
+//    own chained scan. The first place's launch also counts the digits of
+//    every place per segment: its first workgroups count, the later ones bin
+//    (kBinSegCounted in the binning kernel); every binning tile turns its
+//    segment's counts of the place into bin starts itself.
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -106,6 +108,7 @@ __global__ void __launch_bounds__(kClassifyBlock) classify_kernel(ClassifyArgs a
     if (li >= a.max_large || first + tiles > a.max_tiles) {
       atomicOr(&a.plan->error, 1u);  // only reachable with invalid offsets
     } else {
+      a.large_len[li] = len;
       for (uint32_t k = 0; k < tiles; ++k)
         a.tile_info[first + k] = make_uint4(lo + k * T, min(T, len - k * T), lo, li);
     }
@@ -142,118 +145,6 @@ __global__ void __launch_bounds__(256) segment_clear_kernel(SegmentClearArgs a) 
 
 hipError_t launch_segment_clear(const SegmentClearArgs &a, uint32_t grid, hipStream_t stream) {
   hipLaunchKernelGGL(segment_clear_kernel, dim3(grid), dim3(256), 0, stream, a);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- histogram
-// Digit counts of every place per large segment. Workgroups take tiles
-// cyclically, count into LDS (kCopies interleaved copies, as in the upfront
-// histogram) and add the non-zero counts to their segment's histograms.
-template <typename K, bool kOrdered>
-__global__ void __launch_bounds__(256) segment_histogram_kernel(SegmentHistArgs a) {
-  constexpr int kMaxP = static_cast<int>(sizeof(K));
-  constexpr int kCopies = 4;
-  __shared__ uint32_t s_hist[kMaxP * kRadix * kCopies];
-  const K *keys = static_cast<const K *>(a.keys);
-  const int tid = threadIdx.x;
-  const int places = a.places;
-  int shifts[kMaxP];
-  uint32_t masks[kMaxP];
-#pragma unroll
-  for (int j = 0; j < kMaxP; ++j) {
-    const int lo = a.begin_bit + j * kRadixBits;
-    const int hi = min(lo + kRadixBits, a.end_bit);
-    shifts[j] = j < places ? lo : 0;
-    masks[j] = j < places ? ((1u << (hi - lo)) - 1u) : 0u;
-  }
-  uint32_t *my_hist = s_hist + (tid % kCopies);
-  const uint32_t tiles = a.plan->error ? 0u : a.plan->large_tiles;
-  for (int i = tid; i < places * kRadix * kCopies; i += 256) s_hist[i] = 0u;
-  __syncthreads();
-  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-    const uint4 info = a.tile_info[t];
-    constexpr int kBatch = 8;  // independent loads in flight per thread
-    for (uint32_t base = 0; base < info.y; base += 256 * kBatch) {
-      K k[kBatch];
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        const uint32_t i = base + b * 256 + tid;
-        k[b] = i < info.y ? keys[info.x + i] : K(0);
-      }
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        if (base + b * 256 + tid >= info.y) continue;
-        const K o = kOrdered ? ordered_bits(k[b], a.order) : k[b];
-#pragma unroll
-        for (int j = 0; j < kMaxP; ++j)
-          if (j < places)
-            atomicAdd(&my_hist[(j * kRadix + (static_cast<uint32_t>(o >> shifts[j]) & masks[j])) *
-                               kCopies],
-                      1u);
-      }
-    }
-    __syncthreads();
-    uint32_t *dst = a.hist + static_cast<size_t>(info.w) * places * kRadix;
-    for (int i = tid; i < places * kRadix; i += 256) {
-      uint32_t c = 0u;
-#pragma unroll
-      for (int k = 0; k < kCopies; ++k) {
-        c += s_hist[i * kCopies + k];
-        s_hist[i * kCopies + k] = 0u;
-      }
-      if (c != 0u) atomicAdd(&dst[i], c);
-    }
-    __syncthreads();
-  }
-}
-
-// Exclusive sum of every (large segment, place) histogram row, in place: one
-// wavefront per row of 256 counts.
-__global__ void __launch_bounds__(256) segment_scan_kernel(uint32_t *hist,
-                                                            const SegmentPlan *plan, int places) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t wave = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-  const uint32_t waves = gridDim.x * (256 / kWave);
-  const uint32_t rows = plan->error ? 0u : plan->count[kSegClasses] * static_cast<uint32_t>(places);
-  for (uint32_t row = wave; row < rows; row += waves) {
-    uint4 *p = reinterpret_cast<uint4 *>(hist + static_cast<size_t>(row) * kRadix) + lane;
-    const uint4 v = *p;
-    const uint32_t s1 = v.x, s2 = s1 + v.y, s3 = s2 + v.z, total = s3 + v.w;
-    uint32_t incl = total;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t t = __shfl_up(incl, off, kWave);
-      if (lane >= off) incl += t;
-    }
-    const uint32_t e = incl - total;
-    *p = make_uint4(e, e + s1, e + s2, e + s3);
-  }
-}
-
-hipError_t launch_segment_histogram(int key_bits, const SegmentHistArgs &a, uint32_t grid,
-                                    hipStream_t stream) {
-  const bool plain = key_order_is_plain(a.order);
-  if (key_bits == 32) {
-    if (plain)
-      hipLaunchKernelGGL((segment_histogram_kernel<uint32_t, false>), dim3(grid), dim3(256), 0,
-                         stream, a);
-    else
-      hipLaunchKernelGGL((segment_histogram_kernel<uint32_t, true>), dim3(grid), dim3(256), 0,
-                         stream, a);
-  } else {
-    if (plain)
-      hipLaunchKernelGGL((segment_histogram_kernel<uint64_t, false>), dim3(grid), dim3(256), 0,
-                         stream, a);
-    else
-      hipLaunchKernelGGL((segment_histogram_kernel<uint64_t, true>), dim3(grid), dim3(256), 0,
-                         stream, a);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_segment_scan(uint32_t *hist, const SegmentPlan *plan, int places, uint32_t grid,
-                               hipStream_t stream) {
-  hipLaunchKernelGGL(segment_scan_kernel, dim3(grid), dim3(256), 0, stream, hist, plan, places);
   return hipGetLastError();
 }
 

@@ -55,6 +55,12 @@ def temp_error_flag(temp: torch.Tensor) -> int:
     return int(host(temp[:4]).view(np.uint32)[0])
 
 
+def temp_wait_flag(temp: torch.Tensor) -> int:
+    """Word 6 of the plan: set by a binning tile that gave up waiting (for
+    its predecessors' prefixes or for its segment's digit counts)."""
+    return int(host(temp[24:28]).view(np.uint32)[0])
+
+
 def run(ow, keys, off, vals=None, begin=0, end=None, config=None, in_place=False, temp=None):
     """Sort on the GPU; returns (keys, vals, temp)."""
     kb = keys.dtype.itemsize * 8
@@ -83,6 +89,7 @@ def check(ow, keys, off, vals=None, begin=0, end=None, config=None, in_place=Fal
     want_k, want_v = oracle.sort_segments(keys, off, vals, begin, end, 8)
     if keys.size:  # the status word is not written for n == 0
         assert temp_error_flag(temp) == 0, what
+        assert temp_wait_flag(temp) == 0, what
     bad = np.flatnonzero(got_k != want_k)
     assert bad.size == 0, (what, bad[:10], got_k[bad[:5]], want_k[bad[:5]])
     if vals is not None:
@@ -207,6 +214,21 @@ def test_segments_lognormal_mix(ow):
     check(ow, keys, off, np.arange(n, dtype=np.uint32), what="lognormal")
 
 
+def test_segments_bounded_waits(ow):
+    """The first place's launch counts every place's digits and bins: its
+    binning tiles wait until their segment's counts add up to its length.
+    With the default limit no wait gives up and the sort matches the oracle;
+    with a limit of one poll the tiles of a 2^22-key segment give up waiting
+    (for counts or predecessors), record it in the plan, and still end."""
+    off = np.array([0, 1 << 22, (1 << 22) + 3000], dtype=np.int64)
+    n = int(off[-1])
+    keys = W.uniform(91, n)
+    check(ow, keys, off, what="default limit")
+    _, _, temp = run(ow, keys, off, config=ow.make_config(lookback_spin_limit=1))
+    assert temp_error_flag(temp) == 0
+    assert temp_wait_flag(temp) == 1
+
+
 def test_segments_invalid_offsets_write_nothing(ow):
     n = 20000
     keys = W.uniform(15, n)
@@ -241,8 +263,10 @@ def test_segments_trace_launch_sequence(ow):
     ow.sort_segments(tk, to, config=ow.make_config(trace=tr))
     torch.cuda.synchronize()
     kinds = [tr.kinds[i] for i in range(tr.count)]
+    # the first binning launch also counts every place's digits per segment:
+    # no histogram or scan launch of its own
     assert kinds == [ow.KERNEL_CLASSIFY] + [ow.KERNEL_LDS_SORT] * 3 + \
-        [ow.KERNEL_RESET, ow.KERNEL_HISTOGRAM, ow.KERNEL_SCAN] + [ow.KERNEL_BINNING] * 4
+        [ow.KERNEL_RESET] + [ow.KERNEL_BINNING] * 4
 
 
 def test_segments_graph_capture_replays(ow):
