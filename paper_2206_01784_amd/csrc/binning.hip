@@ -786,6 +786,7 @@ __global__ void __launch_bounds__(kBlock)
   X(uint32_t, false, 1024, 11, 0)    \
   X(uint32_t, true, 1024, 11, 0)     \
   X(uint64_t, false, 1024, 9, 0)     \
+  X(uint64_t, true, 1024, 9, 0)      \
   X(uint64_t, false, 256, 8, 0)      \
   X(uint64_t, true, 256, 8, 0)       \
   X(uint64_t, false, 512, 8, 0)      \
@@ -799,7 +800,7 @@ __global__ void __launch_bounds__(kBlock)
   X(uint32_t, false, 1024, 19, 0) \
   X(uint32_t, true, 1024, 18, 0)  \
   X(uint64_t, false, 1024, 9, 0)  \
-  X(uint64_t, true, 1024, 8, 0)
+  X(uint64_t, true, 1024, 9, 0)
 
 #define ONESWEEP_SHAPE_IS(K, V, B, I, R) \
   (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I && s.rank == R)
@@ -828,32 +829,37 @@ size_t binning_tile_items(const BinningShape &s) {
 
 // The autotuned plain configuration: the fastest tile shape per key width,
 // value presence and input size, measured on MI355X over uniform inputs of
-// 2^18..2^28 keys. Small inputs want more, smaller tiles to fill 256 CUs;
-// larger ones the largest tile that two 1024-thread workgroups per CU hold
-// without spilling, since a larger tile spreads the look-back and the
-// workgroup's fixed work over more keys. 32-bit keys (ms per sort):
-// 1024 x 16 from 2^22 (0.107 against 0.119 with 1024 x 11), 1024 x 19
-// from 2^23 (2^28: 2.45 against 2.58 with 1024 x 16 and 2.95 with
-// 1024 x 11). 32-bit pairs: 1024 x 16 from 2^22 (2^26: 1.23 against 1.29
-// with 1024 x 11 and 1.27 with 1024 x 18), 1024 x 18 from 2^28 (4.84
-// against 4.96 with 1024 x 16; it spills a few registers, which costs more
-// than the larger tile saves below 2^28). 64-bit keys 1024 x 9 (3% faster
-// than 1024 x 8); 64-bit pairs stay at 1024 x 8.
+// 2^18..2^28 keys, and over the seeded sweep of 2^17..2^28 keys of every
+// distribution (500 inputs, every tile class timed). Small inputs want more,
+// smaller tiles to fill 256 CUs; larger ones the largest tile that two
+// 1024-thread workgroups per CU hold without spilling, since a larger tile
+// spreads the look-back and the workgroup's fixed work over more keys.
+// 32-bit keys (ms per sort): 1024 x 16 from 3 * 2^20 (2^22: 0.107 against
+// 0.119 with 1024 x 11; the sweep's best between 2^21 and 2^22 was
+// 1024 x 16 or 1024 x 11, 4% faster than 1024 x 11 alone), 1024 x 19 from
+// 2^23 (2^28: 2.45 against 2.58 with 1024 x 16 and 2.95 with 1024 x 11).
+// 32-bit pairs: 1024 x 11 from 2^21 (the sweep: 8% faster than 1024 x 8
+// between 2^21 and 2^22), 1024 x 16 from 2^22 (2^26: 1.23 against 1.29 with
+// 1024 x 11 and 1.27 with 1024 x 18), 1024 x 18 from 2^28 (4.84 against
+// 4.96 with 1024 x 16; it spills a few registers, which costs more than the
+// larger tile saves below 2^28). 64-bit keys 1024 x 9 (3% faster than
+// 1024 x 8); 64-bit pairs 1024 x 9 from 2^21 (the sweep: 1-2% faster than
+// 1024 x 8 at every size from 2^21 to 2^28).
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
   if (key_bits == 64) {
     if (has_values && n < (size_t(3) << 16)) return BinningShape{64, true, 256, 8, kRankBallot};
     if (n < (size_t(1) << 19)) return BinningShape{64, has_values, 512, 8, kRankBallot};
-    if (n >= (size_t(1) << 21) && !has_values) return BinningShape{64, false, 1024, 9, kRankBallot};
+    if (n >= (size_t(1) << 21)) return BinningShape{64, has_values, 1024, 9, kRankBallot};
     return BinningShape{64, has_values, 1024, 8, kRankBallot};
   }
   if (n < (size_t(1) << 18)) return BinningShape{32, has_values, 256, 8, kRankBallot};
   if (n < (size_t(1) << 21)) return BinningShape{32, has_values, 1024, 8, kRankBallot};
   if (has_values) {
-    if (n < (size_t(1) << 22)) return BinningShape{32, true, 1024, 8, kRankBallot};
+    if (n < (size_t(1) << 22)) return BinningShape{32, true, 1024, 11, kRankBallot};
     if (n < (size_t(1) << 28)) return BinningShape{32, true, 1024, 16, kRankBallot};
     return BinningShape{32, true, 1024, 18, kRankBallot};
   }
-  if (n < (size_t(1) << 22)) return BinningShape{32, false, 1024, 11, kRankBallot};
+  if (n < (size_t(3) << 20)) return BinningShape{32, false, 1024, 11, kRankBallot};
   if (n < (size_t(1) << 23)) return BinningShape{32, false, 1024, 16, kRankBallot};
   return BinningShape{32, false, 1024, 19, kRankBallot};
 }

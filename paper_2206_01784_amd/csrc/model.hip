@@ -254,8 +254,10 @@ namespace {
 constexpr size_t kLearnedMinN = size_t(1) << 26;
 constexpr size_t kLearnedMaxN = size_t(1) << 28;
 // A class replaces the autotuned default only when predicted faster by more
-// than this (log-time units, about 2%).
-constexpr float kSelectMargin = 0.02f;
+// than this (log-time units, about 5%). Over the held-out sweep the best
+// class beats the default by 0.4% on average at these sizes, while a 2%
+// margin let through mispredictions that cost up to 20%.
+constexpr float kSelectMargin = 0.05f;
 // The host-mapped choice word before the selection kernel writes it (the
 // kernel writes a class index or -1).
 constexpr int kChoicePending = -2;

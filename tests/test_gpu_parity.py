@@ -371,7 +371,7 @@ def test_graph_capture_replays(ow):
 
 RTS_SHAPES = {
     32: [(256, 8), (512, 16), (1024, 8), (1024, 11), (1024, 16), (1024, 18), (1024, 19)],
-    64: [(256, 8), (512, 8), (1024, 8)],
+    64: [(256, 8), (512, 8), (1024, 8), (1024, 9)],
 }
 
 
