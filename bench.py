@@ -45,6 +45,7 @@ WORKLOADS = {
     "u64_pairs_uniform": (64, True, "uniform", 27),
     "u32_keys_uniform_2p20": (32, False, "uniform", 20),
     "u32_keys_uniform_2p30": (32, False, "uniform", 30),
+    "u32_keys_uniform_2p31": (32, False, "uniform", 31),
 }
 # Batched segmented workload: S segments with log-normal lengths (median 2000,
 # sigma 1.5, cap 2^22) scaled to 2^26 keys in total; uniform uint32 keys,
@@ -376,7 +377,9 @@ def segments_leg(args, S, log2n, tune=False, with_loops=True):
                                    ms_per_step)
     return {"n": n, "lengths": lengths, "off": off, "keys": keys, "vals": vals,
             "ms_per_step": ms_per_step, "value": value, "block": block, "ipt": ipt,
-            "limits": limits, "tuned": tune, "tile": ow.tile_items(32, True, cfg, n),
+            "limits": limits, "tuned": tune,
+            # tile_items reports the plain sort's table; segments have their own
+            "tile": ow.tile_items(32, True, cfg, n) if block else "segmented default",
             "per_kind": per_kind, "baselines": baselines}
 
 
@@ -737,7 +740,9 @@ def main():
         """`count` configs, each recording HIP events around every launch on
         the stream the kernels run on."""
         rts_alg = alg == ow.ALGORITHM_REDUCE_THEN_SCAN
-        launches = min(ow.TRACE_MAX, 3 + places * (3 if rts_alg else strips) + 1)
+        # from 2^31 keys the histogram runs over portions of at most 2^30 keys
+        portions = -(-n // (1 << 30)) if n >= (1 << 31) else 1
+        launches = min(ow.TRACE_MAX, 2 + portions + places * (3 if rts_alg else strips) + 1)
         cfgs, holders = [], []
         for _ in range(count):
             evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * launches)]

@@ -315,7 +315,8 @@ onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
 /*
  * Autotuner of the segmented sort (not in the paper): times
  * onesweep_sort_segments on the caller's data for every built tile shape of
- * the segmented path (32-bit keys: 256x8, 256x16, 512x16, 1024x8, 1024x11;
+ * the segmented path (32-bit keys: 256x8, 256x16, 512x16, 1024x8, 1024x11,
+ * 1024x16;
  * 64-bit keys: 256x8, 256x16, 512x8, 1024x8, 1024x9) crossed with seven
  * settings of the segment class limits
  * (`repetitions` timed runs each, after one warm-up), writes the fastest

@@ -1135,13 +1135,14 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
   // Candidates: every tile shape built for the segmented path, crossed with
   // class limits that move segments between the LDS classes and the tile
   // path.
-  static const int kShapes32[][2] = {{256, 8}, {256, 16}, {512, 16}, {1024, 8}, {1024, 11}};
+  static const int kShapes32[][2] = {{256, 8},  {256, 16},  {512, 16},
+                                     {1024, 8}, {1024, 11}, {1024, 16}};
   static const int kShapes64[][2] = {{256, 8}, {256, 16}, {512, 8}, {1024, 8}, {1024, 9}};
   static const int kLimits[][3] = {{0, 0, 0},   {0, 0, 4096},  {0, 0, 2048}, {0, 0, -1},
                                    {0, -1, 0},  {-1, 0, 0},    {256, 1024, 4096}};
-  constexpr int kNumShapes = sizeof(kShapes32) / sizeof(kShapes32[0]);
   constexpr int kNumLimits = sizeof(kLimits) / sizeof(kLimits[0]);
-  static_assert(sizeof(kShapes64) == sizeof(kShapes32), "one shape list per key width");
+  const int num_shapes = key_bits == 64 ? static_cast<int>(sizeof(kShapes64) / sizeof(kShapes64[0]))
+                                        : static_cast<int>(sizeof(kShapes32) / sizeof(kShapes32[0]));
   // The key order comes in through *cfg_out and is kept by every candidate.
   const int key_type = cfg_out ? cfg_out->key_type : ONESWEEP_KEY_UNSIGNED;
   const int descending = cfg_out ? cfg_out->descending : 0;
@@ -1155,7 +1156,7 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
     for (int k = 0; k < 3; ++k) c.segment_limits[k] = kLimits[i % kNumLimits][k];
     return c;
   };
-  const int count = kNumShapes * kNumLimits;
+  const int count = num_shapes * kNumLimits;
   g_error[0] = '\0';
   if (temp_bytes == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp_bytes is NULL");
   if (d_temp != nullptr && cfg_out == nullptr)

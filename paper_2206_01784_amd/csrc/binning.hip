@@ -279,26 +279,36 @@ __global__ void __launch_bounds__(kBlock)
 
   // The bin starts of this place, loaded before the keys so that waiting for
   // them does not wait for the keys; kept in s_gbase until the look-back.
-  // A segment's tile derives them from the segment's digit counts: each of
-  // threads 0..255 holds its digit's exclusive sum within its wave here and
-  // adds the lower waves' totals (s_seg_sum) at the look-back.
+  // A segment's tile derives them from the segment's digit counts of the
+  // place (seg_count, loaded here): after the key loads are issued, threads
+  // 0..255 scan the counts within their wave, and each adds the lower waves'
+  // totals (s_seg_sum) at the look-back.
   Idx bin_start_load = 0u;
+  uint32_t seg_count = 0u;
+  const uint32_t *seg_counts = nullptr;
   if constexpr (kSeg) {
-    const uint32_t *counts =
+    seg_counts =
         a.seg.counts + (static_cast<size_t>(seg_info.w) * a.seg.places + a.place) * kRadix;
-    uint32_t c = 0u;
+    if constexpr (!kCounted)
+      if (tid < kRadix) seg_count = seg_counts[tid];
+  } else if (tid < kRadix) {
+    bin_start_load = a.bin_offsets[tid];
+  }
+  // Segmented tiles: turn the counts into this thread's exclusive digit sum
+  // within its wave. In the launch that also counts, first wait for the
+  // counts: they only grow and their final values add up to the segment's
+  // length, so a read of all 256 that adds up to the length has read every
+  // final value (no ordering between the counters is needed, only each
+  // counter's own).
+  auto segment_bin_starts = [&]() {
     if constexpr (kCounted) {
-      // Counting runs in this launch. The counts only grow and their final
-      // values add up to the segment's length, so a read of all 256 that
-      // adds up to the length has read every final value: no ordering
-      // between the counters is needed, only each counter's own.
       const uint32_t len = a.seg.large_len[seg_info.w];
       uint32_t rounds = 0u;
       while (true) {
         if (tid < kRadix)
-          c = __hip_atomic_load(const_cast<uint32_t *>(counts + tid), __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t sum = tid < kRadix ? c : 0u;
+          seg_count = __hip_atomic_load(const_cast<uint32_t *>(seg_counts + tid),
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t sum = tid < kRadix ? seg_count : 0u;
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
         if (tid < kRadix && lane == 0) s_seg_sum[wave] = sum;
@@ -315,22 +325,18 @@ __global__ void __launch_bounds__(kBlock)
         }
         __builtin_amdgcn_s_sleep(2);
       }
-    } else if (tid < kRadix) {
-      c = counts[tid];
     }
     if (tid < kRadix) {
-      uint32_t incl = c;
+      uint32_t incl = seg_count;
 #pragma unroll
       for (int off = 1; off < kWave; off <<= 1) {
         const uint32_t t = __shfl_up(incl, off, kWave);
         if (lane >= off) incl += t;
       }
       if (lane == kWave - 1) s_seg_sum[wave] = incl;
-      bin_start_load = incl - c;
+      bin_start_load = incl - seg_count;
     }
-  } else if (tid < kRadix) {
-    bin_start_load = a.bin_offsets[tid];
-  }
+  };
 
   // 1. Load. For ranking, a lane past the end of a ragged tile holds the key
   // whose ordered bits are all ones: its digit is the largest the place can
@@ -366,6 +372,7 @@ __global__ void __launch_bounds__(kBlock)
         key[i] = src[idx < tile_end ? idx : tile_end - 1u];
       }
     }
+    if constexpr (kSeg) segment_bin_starts();
     if (tid < kRadix) s_gbase[tid] = bin_base + bin_start_load;
     auto ranked = [&](int i) -> K {
       if constexpr (kFull) return key[i];
@@ -765,6 +772,8 @@ __global__ void __launch_bounds__(kBlock)
   X(uint64_t, true, 1024, 8, 0)            \
   X(uint32_t, false, 1024, 11, 0)          \
   X(uint32_t, true, 1024, 11, 0)           \
+  X(uint32_t, false, 1024, 16, 0)          \
+  X(uint32_t, true, 1024, 16, 0)           \
   X(uint64_t, false, 1024, 9, 0)           \
   X(uint64_t, true, 1024, 9, 0)
 
@@ -866,16 +875,16 @@ BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
 
 // The default tile shape of the segmented sort's large segments, measured on
 // MI355X with the batched workload (20000 log-normal segments, 2^26 keys,
-// graph replay): 32-bit keys 256 x 16 (0.87-0.90 ms against 0.91 with
-// 1024 x 8 and 0.92 with 1024 x 11), 32-bit pairs 512 x 16 (1.20 against
-// 1.29 and 1.25), 64-bit keys 1024 x 9 (2.25 against 2.33 with 1024 x 8),
-// 64-bit pairs 1024 x 8 (3.11, as fast as 1024 x 9).
+// eager, two streams; ms per sort): 32-bit keys 512 x 16 (0.79, against
+// 0.79 with 1024 x 16, 0.82 with 1024 x 11 and 0.96 with 256 x 16), 32-bit
+// pairs 1024 x 16 (1.01, against 1.06 with 1024 x 11 and 1.13 with
+// 512 x 16; 1.09 against 1.17 under graph replay), 64-bit keys 1024 x 9
+// (2.20 against 2.25 with 1024 x 8), 64-bit pairs 1024 x 9 (3.03 against
+// 3.09 with 1024 x 8).
 BinningShape segment_default_shape(int key_bits, bool has_values) {
-  if (key_bits == 64)
-    return has_values ? BinningShape{64, true, 1024, 8, kRankBallot}
-                      : BinningShape{64, false, 1024, 9, kRankBallot};
-  return has_values ? BinningShape{32, true, 512, 16, kRankBallot}
-                    : BinningShape{32, false, 256, 16, kRankBallot};
+  if (key_bits == 64) return BinningShape{64, has_values, 1024, 9, kRankBallot};
+  return has_values ? BinningShape{32, true, 1024, 16, kRankBallot}
+                    : BinningShape{32, false, 512, 16, kRankBallot};
 }
 
 hipError_t launch_binning(const BinningShape &s, int mode, const void *args, uint32_t grid,

@@ -193,12 +193,14 @@ constexpr int lds_sort_waves_per_eu() {
   return kBlock >= 1024 && sizeof(K) == 4 ? 8 : 4;
 }
 
-// Wave-level digit match of the LDS sort: one ballot per digit bit, or
-// 64-bit presence masks in LDS (an atomic OR per lane and one read per
-// batch: far fewer vector instructions, which is what bounds this kernel).
-// The masks overlay the tile buffer, which is idle while keys are ranked.
+// Wave-level digit match of the LDS sort: one ballot per digit bit (the
+// default: with the three-input OR-of-XOR per ballot half, 20000 log-normal
+// segments of 2^26 32-bit keys sort in 0.75 ms against 0.79 with masks;
+// pairs and 64-bit keys are even), or 64-bit presence masks in LDS (an
+// atomic OR per lane and one read per batch). The masks overlay the tile
+// buffer, which is idle while keys are ranked.
 #ifndef ONESWEEP_LDS_PRESENCE
-#define ONESWEEP_LDS_PRESENCE 1
+#define ONESWEEP_LDS_PRESENCE 0
 #endif
 constexpr bool kLdsPresence = ONESWEEP_LDS_PRESENCE != 0;
 
@@ -272,13 +274,19 @@ __global__ void __launch_bounds__(kBlock)
             peers_lo = static_cast<uint32_t>(peers);
             peers_hi = static_cast<uint32_t>(peers >> 32);
           } else {
+            // lanes holding another digit: per bit, the vote XOR this lane's
+            // bit, ORed in (one three-input operation per 32-lane half)
+            uint32_t mis_lo = 0u, mis_hi = 0u;
 #pragma unroll
             for (int b = 0; b < kRadixBits; ++b) {
-              const int own = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);
-              const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0);
-              peers_lo &= ~(static_cast<uint32_t>(vote) ^ static_cast<uint32_t>(own));
-              peers_hi &= ~(static_cast<uint32_t>(vote >> 32) ^ static_cast<uint32_t>(own));
+              uint32_t own = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(d), b, 1));
+              asm volatile("" : "+v"(own));  // vote on the extracted bit: one compare
+              const uint64_t vote = __builtin_amdgcn_ballot_w64(own != 0u);
+              mis_lo = __builtin_amdgcn_bitop3_b32(mis_lo, static_cast<uint32_t>(vote), own, 0xF6);
+              mis_hi = __builtin_amdgcn_bitop3_b32(mis_hi, static_cast<uint32_t>(vote >> 32), own, 0xF6);
             }
+            peers_lo = ~mis_lo;
+            peers_hi = ~mis_hi;
           }
           uint32_t &c = s_cnt[wave * kRadix + d];
           const uint32_t prior = c;
