@@ -172,7 +172,7 @@ struct LdsSortArgs {
   KeyOrder order;
 };
 int lds_class_capacity(int cls);
-int lds_class_block(int cls);
+int lds_class_block(int key_bits, bool has_values, int cls);
 hipError_t lds_sort_blocks_per_cu(int key_bits, bool has_values, int cls, int *blocks);
 hipError_t launch_lds_sort(int key_bits, bool has_values, const LdsSortArgs &a, uint32_t grid,
                            hipStream_t stream);

@@ -5,8 +5,8 @@
 //
 //  - classify: one thread per segment validates its offsets and assigns the
 //    segment to a class by length: three classes small enough to be sorted
-//    inside one workgroup's LDS (64, 256 or 1024 threads, 8 keys per thread)
-//    and a "large" class. Each large segment is cut into binning tiles whose
+//    inside one workgroup's LDS (up to 512, 2048 and 8192 keys) and a
+//    "large" class. Each large segment is cut into binning tiles whose
 //    descriptors are consecutive.
 //  - LDS sort: one workgroup per segment loads it once, runs the LSD passes
 //    over 8-bit digits in LDS with the same wave64 multi-split ranking as the
@@ -186,7 +186,7 @@ hipError_t launch_segment_copy(const SegmentCopyArgs &a, uint32_t grid, hipStrea
 // padded with all-ones keys, which rank after every real key and so stay in
 // the slots past the end. Keys are held as their ordered bits (signed,
 // floating-point and descending orders) from load to store.
-// The 1024-thread class with 32-bit keys is held to 64 registers so two
+// The 1024-thread class (32-bit keys only) is held to 64 registers so two
 // workgroups fit a CU.
 template <typename K, int kBlock>
 constexpr int lds_sort_waves_per_eu() {
@@ -341,47 +341,59 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Classes: 64, 256 and 1024 threads, 8 keys per thread.
-constexpr int kLdsIpt = 8;
-constexpr int kLdsBlock[kSegClasses] = {64, 256, 1024};
+// Classes of 512, 2048 and 8192 keys: 64 and 256 threads with 8 keys each;
+// the largest class with 1024 threads x 8 keys for 32-bit keys only and
+// 512 threads x 16 keys otherwise. Measured on 20000 log-normal segments of
+// 2^26 keys in all (ms per sort, 1024 x 8 against 512 x 16 in that class):
+// 32-bit keys 0.73 / 0.75, 32-bit pairs 1.01 / 0.99, 64-bit keys 2.19 / 1.87,
+// 64-bit pairs 3.02 / 2.54 (64-bit 1024-thread workgroups fit one per CU).
+constexpr int kLdsCapacity[kSegClasses] = {512, 2048, 8192};
 
-int lds_class_capacity(int cls) { return kLdsBlock[cls] * kLdsIpt; }
+int lds_class_capacity(int cls) { return kLdsCapacity[cls]; }
 
-int lds_class_block(int cls) { return kLdsBlock[cls]; }
+int lds_class_block(int key_bits, bool has_values, int cls) {
+  if (cls == 0) return 64;
+  if (cls == 1) return 256;
+  return key_bits == 32 && !has_values ? 1024 : 512;
+}
 
 namespace {
 template <typename K, bool V, int B>
 const void *lds_kernel_ptr(bool ordered) {
-  return ordered ? reinterpret_cast<const void *>(&lds_sort_kernel<K, V, B, kLdsIpt, true>)
-                 : reinterpret_cast<const void *>(&lds_sort_kernel<K, V, B, kLdsIpt, false>);
+  constexpr int I = B <= 256 ? 8 : 8192 / B;  // keys per thread
+  return ordered ? reinterpret_cast<const void *>(&lds_sort_kernel<K, V, B, I, true>)
+                 : reinterpret_cast<const void *>(&lds_sort_kernel<K, V, B, I, false>);
 }
 
 const void *lds_kernel(int key_bits, bool has_values, int cls, bool ordered) {
-#define ONESWEEP_LDS_PICK(B)                                                                \
-  if (key_bits == 32)                                                                       \
-    return has_values ? lds_kernel_ptr<uint32_t, true, B>(ordered)                          \
-                      : lds_kernel_ptr<uint32_t, false, B>(ordered);                        \
-  return has_values ? lds_kernel_ptr<uint64_t, true, B>(ordered)                            \
-                    : lds_kernel_ptr<uint64_t, false, B>(ordered);
   switch (cls) {
-    case 0: {
-      ONESWEEP_LDS_PICK(64)
-    }
-    case 1: {
-      ONESWEEP_LDS_PICK(256)
-    }
-    default: {
-      ONESWEEP_LDS_PICK(1024)
-    }
+    case 0:
+      if (key_bits == 32)
+        return has_values ? lds_kernel_ptr<uint32_t, true, 64>(ordered)
+                          : lds_kernel_ptr<uint32_t, false, 64>(ordered);
+      return has_values ? lds_kernel_ptr<uint64_t, true, 64>(ordered)
+                        : lds_kernel_ptr<uint64_t, false, 64>(ordered);
+    case 1:
+      if (key_bits == 32)
+        return has_values ? lds_kernel_ptr<uint32_t, true, 256>(ordered)
+                          : lds_kernel_ptr<uint32_t, false, 256>(ordered);
+      return has_values ? lds_kernel_ptr<uint64_t, true, 256>(ordered)
+                        : lds_kernel_ptr<uint64_t, false, 256>(ordered);
+    default:
+      if (key_bits == 32)
+        return has_values ? lds_kernel_ptr<uint32_t, true, 512>(ordered)
+                          : lds_kernel_ptr<uint32_t, false, 1024>(ordered);
+      return has_values ? lds_kernel_ptr<uint64_t, true, 512>(ordered)
+                        : lds_kernel_ptr<uint64_t, false, 512>(ordered);
   }
-#undef ONESWEEP_LDS_PICK
 }
 }  // namespace
 
 hipError_t lds_sort_blocks_per_cu(int key_bits, bool has_values, int cls, int *blocks) {
   // the ordered variants differ only at load and store
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks, lds_kernel(key_bits, has_values, cls, false), kLdsBlock[cls], 0);
+      blocks, lds_kernel(key_bits, has_values, cls, false),
+      lds_class_block(key_bits, has_values, cls), 0);
 }
 
 hipError_t launch_lds_sort(int key_bits, bool has_values, const LdsSortArgs &a, uint32_t grid,
@@ -389,7 +401,8 @@ hipError_t launch_lds_sort(int key_bits, bool has_values, const LdsSortArgs &a, 
   const void *k = lds_kernel(key_bits, has_values, a.cls, !key_order_is_plain(a.order));
   LdsSortArgs copy = a;
   void *params[] = {&copy};
-  return hipLaunchKernel(k, dim3(grid), dim3(kLdsBlock[a.cls]), params, 0, stream);
+  return hipLaunchKernel(k, dim3(grid), dim3(lds_class_block(key_bits, has_values, a.cls)),
+                         params, 0, stream);
 }
 
 }  // namespace onesweep
