@@ -126,7 +126,11 @@ typedef struct {
  * accepted; others return ONESWEEP_ERROR_UNSUPPORTED.
  */
 typedef struct {
-    int digit_bits;          /* 0 or 8 */
+    int digit_bits;          /* width d of a digit place: 0 (= 8) or 4..8; the sort
+                                makes ceil((end_bit - begin_bit) / d) passes, at
+                                most 8 (more returns ONESWEEP_ERROR_UNSUPPORTED).
+                                8 is fastest on MI355X (Table 2's trade-off: a
+                                binning pass costs about the same at any width) */
     int block_threads;       /* binning workgroup size: 256, 512 or 1024 */
     int items_per_thread;    /* binning items per thread */
     int hist_blocks_per_cu;  /* histogram grid = CUs x this (persistent, tile-cyclic) */
@@ -240,8 +244,9 @@ onesweep_status_t onesweep_sort_keys_noalloc(const void *d_keys_in, void *d_keys
  * Phase 1 alone (Section 3, upfront histogram kernel): d_hist[j * 256 + v]
  * receives the number of keys whose digit at place j is v (digits of the
  * key bits as cfg's key_type and descending order them), for all
- * p = ceil((end_bit - begin_bit) / 8) places. d_hist must hold p * 256
- * uint32 words; it is cleared first. n < 2^30.
+ * p = ceil((end_bit - begin_bit) / d) places of d = cfg's digit_bits (8 by
+ * default) bits; entries v >= 2^d stay 0. d_hist must hold p * 256 uint32
+ * words; it is cleared first. n < 2^30.
  */
 onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits, int begin_bit,
                                      int end_bit, uint32_t *d_hist,
@@ -318,7 +323,8 @@ onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
  * the segmented path (32-bit keys: 256x8, 256x16, 512x16, 1024x8, 1024x11,
  * 1024x16;
  * 64-bit keys: 256x8, 256x16, 512x8, 1024x8, 1024x9) crossed with seven
- * settings of the segment class limits
+ * settings of the segment class limits and with 8- and 7-bit digits (7 only
+ * where the bit range makes at most 8 places)
  * (`repetitions` timed runs each, after one warm-up), writes the fastest
  * configuration to *cfg_out and leaves the output sorted by it. Arguments as
  * in onesweep_sort_segments, except that input and output must not alias

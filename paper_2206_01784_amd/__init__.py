@@ -264,12 +264,13 @@ def sort_pairs(keys: torch.Tensor, values: torch.Tensor, begin_bit: int = 0,
 def histogram(keys: torch.Tensor, begin_bit: int = 0, end_bit: int | None = None,
               out: torch.Tensor | None = None, config: Config | None = None,
               stream=None, descending: bool = False) -> torch.Tensor:
-    """Phase 1 alone: uint32 digit counts of every 8-bit place of the ordered
-    key bits, shape (p, 256)."""
+    """Phase 1 alone: uint32 digit counts of every place of the ordered key
+    bits (config.digit_bits wide, 8 by default), shape (p, 256)."""
     kb = _key_bits(keys)
     config = _ordered_config(config, keys, descending)
     end_bit = kb if end_bit is None else end_bit
-    p = (end_bit - begin_bit + RADIX_BITS - 1) // RADIX_BITS
+    d = config.digit_bits if config is not None and config.digit_bits else RADIX_BITS
+    p = (end_bit - begin_bit + d - 1) // d
     if out is None:
         out = torch.empty((max(p, 0), RADIX), dtype=torch.uint32, device=keys.device)
     if p == 0:

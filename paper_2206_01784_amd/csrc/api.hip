@@ -56,9 +56,14 @@ constexpr int kDefaultStripLog2 = 29;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int num_places(int begin_bit, int end_bit) {
-  return (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+int num_places(int begin_bit, int end_bit, int digit_bits) {
+  return (end_bit - begin_bit + digit_bits - 1) / digit_bits;
 }
+
+// Smallest digit width built: narrower digits gain nothing on this GPU (a
+// binning pass costs the same at every width from 5 to 8 bits) and only add
+// passes.
+constexpr int kMinDigitBits = 4;
 
 // Compute units of the current device, cached per device id.
 std::atomic<int> g_cus[64];
@@ -86,6 +91,7 @@ onesweep_status_t device_cus(int *cus) {
 // Resolved kernel configuration.
 struct Resolved {
   BinningShape shape;
+  int digit_bits;  // width of a digit place, 4..8 (places of a sort: at most 8)
   int hist_blocks_per_cu;
   int strip_log2;
   int algorithm;  // onesweep_algorithm_t
@@ -128,14 +134,17 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
   // fit a CU: a grid of two per CU is resident at once (at 2^28 u32 keys
   // 244 us against 250 us with four per CU, which runs in two rounds).
   r->hist_blocks_per_cu = 2;
+  r->digit_bits = kRadixBits;
   r->algorithm = ONESWEEP_ALGORITHM_ONESWEEP;
   r->strip_log2 = kDefaultStripLog2;
   r->order = key_order(key_bits, ONESWEEP_KEY_UNSIGNED, false);
   r->spin_limit = kDefaultSpinLimit;
   r->trace = nullptr;
   if (cfg != nullptr) {
-    if (cfg->digit_bits != 0 && cfg->digit_bits != kRadixBits)
-      return fail(ONESWEEP_ERROR_UNSUPPORTED, "digit_bits %d not built (only 8)", cfg->digit_bits);
+    if (cfg->digit_bits != 0 && (cfg->digit_bits < kMinDigitBits || cfg->digit_bits > kRadixBits))
+      return fail(ONESWEEP_ERROR_UNSUPPORTED, "digit_bits %d not built (%d to %d)",
+                  cfg->digit_bits, kMinDigitBits, kRadixBits);
+    if (cfg->digit_bits != 0) r->digit_bits = cfg->digit_bits;
     if (cfg->block_threads != 0) r->shape.block = cfg->block_threads;
     if (cfg->items_per_thread != 0) r->shape.ipt = cfg->items_per_thread;
     if (cfg->hist_blocks_per_cu < 0 || cfg->hist_blocks_per_cu > 64)
@@ -303,6 +312,16 @@ onesweep_status_t check_common(size_t *temp_bytes, size_t n, int key_bits, int b
   return ONESWEEP_SUCCESS;
 }
 
+// Digit places of [begin_bit, end_bit) at the resolved digit width; a sort
+// covers at most kMaxPlaces of them.
+onesweep_status_t places_of(int begin_bit, int end_bit, const Resolved &rc, int *places) {
+  *places = num_places(begin_bit, end_bit, rc.digit_bits);
+  if (*places > kMaxPlaces)
+    return fail(ONESWEEP_ERROR_UNSUPPORTED, "%d-bit digits make %d places of bits [%d, %d); at most %d",
+                rc.digit_bits, *places, begin_bit, end_bit, kMaxPlaces);
+  return ONESWEEP_SUCCESS;
+}
+
 onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_in,
                             void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
                             bool has_values, size_t n, int key_bits, int begin_bit, int end_bit,
@@ -313,7 +332,8 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
   if (st) return st;
   Resolved rc;
   if ((st = resolve(key_bits, has_values, n, cfg, &rc, kCallSort))) return st;
-  const int places = num_places(begin_bit, end_bit);
+  int places = 0;
+  if ((st = places_of(begin_bit, end_bit, rc, &places))) return st;
   size_t tile = binning_tile_items(rc.shape);
   const bool rts = rc.algorithm == ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN;
   if (late && (rts || n > kLateChoiceMaxN || late->layout_tile == 0))
@@ -401,14 +421,31 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
 
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "clear",
                   launch_fill_zero(temp + L.hist, L.zero_end - L.hist, stream_grid, stream));
-  // Histogram portions of at most 2^30 keys (one launch below 2^30 keys).
+  // Histogram portions of at most 2^30 keys (one launch below 2^30 keys);
+  // one launch counts at most one place per key byte, so digits narrower
+  // than 8 bits over more places take a launch per group of places. With a
+  // late tile choice the selection kernel (one 1024-thread workgroup) runs
+  // beside the histogram: one histogram workgroup fewer per XCD (workgroups
+  // go to the eight XCDs in turn, and so may the selection's) leaves it room
+  // on a CU from the start; else it waits for the histogram's workgroups to
+  // finish, and the binning passes wait for it.
+  constexpr uint32_t kXcds = 8;
+  const int group = key_bits / 8;
+  const uint32_t hist_grid =
+      static_cast<uint32_t>(cus * rc.hist_blocks_per_cu) - (late != nullptr ? kXcds : 0u);
   for (size_t done = 0; done < n; done += kHistPortion) {
     const size_t part = std::min(kHistPortion, n - done);
-    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
-                    launch_histogram(key_bits, static_cast<const char *>(keys_in) + done * kb,
-                                     hist, hist64, static_cast<uint32_t>(part), begin_bit,
-                                     end_bit, places, rc.order,
-                                     static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), stream));
+    for (int g = 0; g < places; g += group) {
+      const int lo = begin_bit + g * rc.digit_bits;
+      const int hi = std::min(end_bit, lo + group * rc.digit_bits);
+      const int gp = std::min(group, places - g);
+      ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
+                      launch_histogram(key_bits, static_cast<const char *>(keys_in) + done * kb,
+                                       hist ? hist + static_cast<size_t>(g) * kRadix : nullptr,
+                                       hist64 ? hist64 + static_cast<size_t>(g) * kRadix : nullptr,
+                                       static_cast<uint32_t>(part), lo, hi, gp, rc.digit_bits,
+                                       rc.order, hist_grid, stream));
+    }
   }
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_SCAN, "scan",
                   launch_scan(hist, hist64, offsets, offsets64, plan, places, n, alias, stream));
@@ -440,8 +477,8 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
     using Idx = decltype(idx_tag);
     Idx *strip_offsets = reinterpret_cast<Idx *>(temp + L.strip_offsets);
     const Idx *place_offsets = reinterpret_cast<const Idx *>(temp + L.offsets) + j * kRadix;
-    const int lo = begin_bit + j * kRadixBits;
-    const int width = (lo + kRadixBits <= end_bit) ? kRadixBits : end_bit - lo;
+    const int lo = begin_bit + j * rc.digit_bits;
+    const int width = (lo + rc.digit_bits <= end_bit) ? rc.digit_bits : end_bit - lo;
     // Onesweep: place j's own status words; reduce-then-scan: the shared
     // count table, filled by the upsweep and scanned before the downsweep.
     uint32_t *table = rts ? status : status + j * status_stride;
@@ -659,7 +696,8 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   if ((st = resolve(key_bits, has_values, n, cfg, &rc, kCallSegments))) return st;
   uint32_t limit[kSegClasses];
   if ((st = segment_limits(cfg, limit))) return st;
-  const int places = num_places(begin_bit, end_bit);
+  int places = 0;
+  if ((st = places_of(begin_bit, end_bit, rc, &places))) return st;
   const size_t tile = binning_tile_items(rc.shape);
   const SegmentLayout L =
       segment_layout(n, num_segments, key_bits, has_values, places, tile, limit);
@@ -790,6 +828,7 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
     la.begin_bit = begin_bit;
     la.end_bit = end_bit;
     la.places = places;
+    la.digit_bits = rc.digit_bits;
     la.order = rc.order;
     const uint32_t grid =
         std::min<uint32_t>(L.capacity[c], static_cast<uint32_t>(cus) * static_cast<uint32_t>(per_cu));
@@ -833,11 +872,12 @@ onesweep_status_t segments_impl(void *d_temp, size_t *temp_bytes, const void *ke
   seg.places = places;
   seg.begin_bit = begin_bit;
   seg.end_bit = end_bit;
+  seg.digit_bits = rc.digit_bits;
   for (int j = 0; j < places; ++j) {
     const int mode = j == 0 ? kBinSegCounted : kBinSegmented;
     const uint32_t grid = (j == 0 ? 2u : 1u) * L.max_tiles;
-    const int lo = begin_bit + j * kRadixBits;
-    const int width = (lo + kRadixBits <= end_bit) ? kRadixBits : end_bit - lo;
+    const int lo = begin_bit + j * rc.digit_bits;
+    const int width = (lo + rc.digit_bits <= end_bit) ? rc.digit_bits : end_bit - lo;
     const int from = buffer_after(j), to = buffer_after(j + 1);
     if (key_bits == 32) {
       BinningArgs<uint32_t> a{};
@@ -994,7 +1034,8 @@ onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits,
   if (st) return st;
   Resolved rc;
   if ((st = resolve(key_bits, false, n, cfg, &rc))) return st;
-  const int places = num_places(begin_bit, end_bit);
+  int places = 0;
+  if ((st = places_of(begin_bit, end_bit, rc, &places))) return st;
   if (places == 0) return ONESWEEP_SUCCESS;
   if (!d_hist) return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_hist is NULL");
   if (n > 0 && !d_keys) return fail(ONESWEEP_ERROR_INVALID_VALUE, "d_keys is NULL");
@@ -1009,10 +1050,16 @@ onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits,
   ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_RESET, "clear",
                   launch_fill_zero(d_hist, sizeof(uint32_t) * places * kRadix, 1, s));
   if (n == 0) return ONESWEEP_SUCCESS;
-  ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
-                  launch_histogram(key_bits, d_keys, d_hist, nullptr, static_cast<uint32_t>(n),
-                                   begin_bit, end_bit, places, rc.order,
-                                   static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), s));
+  const int group = key_bits / 8;  // places one histogram launch counts
+  for (int g = 0; g < places; g += group) {
+    const int lo = begin_bit + g * rc.digit_bits;
+    const int hi = std::min(end_bit, lo + group * rc.digit_bits);
+    ONESWEEP_LAUNCH(tr, ONESWEEP_KERNEL_HISTOGRAM, "histogram",
+                    launch_histogram(key_bits, d_keys, d_hist + static_cast<size_t>(g) * kRadix,
+                                     nullptr, static_cast<uint32_t>(n), lo, hi,
+                                     std::min(group, places - g), rc.digit_bits, rc.order,
+                                     static_cast<uint32_t>(cus * rc.hist_blocks_per_cu), s));
+  }
   return ONESWEEP_SUCCESS;
 }
 
@@ -1140,7 +1187,11 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
   static const int kShapes64[][2] = {{256, 8}, {256, 16}, {512, 8}, {1024, 8}, {1024, 9}};
   static const int kLimits[][3] = {{0, 0, 0},   {0, 0, 4096},  {0, 0, 2048}, {0, 0, -1},
                                    {0, -1, 0},  {-1, 0, 0},    {256, 1024, 4096}};
+  // Digit widths: 8 bits, and 7 (one more place for 32-bit keys, fewer
+  // buckets per pass); wider places than 8 bits are not built.
+  static const int kDigits[] = {8, 7};
   constexpr int kNumLimits = sizeof(kLimits) / sizeof(kLimits[0]);
+  constexpr int kNumDigits = sizeof(kDigits) / sizeof(kDigits[0]);
   const int num_shapes = key_bits == 64 ? static_cast<int>(sizeof(kShapes64) / sizeof(kShapes64[0]))
                                         : static_cast<int>(sizeof(kShapes32) / sizeof(kShapes32[0]));
   // The key order comes in through *cfg_out and is kept by every candidate.
@@ -1151,12 +1202,18 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
     c.key_type = key_type;
     c.descending = descending;
     const int(*shapes)[2] = key_bits == 64 ? kShapes64 : kShapes32;
-    c.block_threads = shapes[i / kNumLimits][0];
-    c.items_per_thread = shapes[i / kNumLimits][1];
-    for (int k = 0; k < 3; ++k) c.segment_limits[k] = kLimits[i % kNumLimits][k];
+    const int shape = i / (kNumLimits * kNumDigits);
+    c.block_threads = shapes[shape][0];
+    c.items_per_thread = shapes[shape][1];
+    for (int k = 0; k < 3; ++k) c.segment_limits[k] = kLimits[(i / kNumDigits) % kNumLimits][k];
+    c.digit_bits = kDigits[i % kNumDigits];
     return c;
   };
-  const int count = num_shapes * kNumLimits;
+  // a digit width whose places would exceed a sort's is not a candidate
+  auto applies = [&](int i) {
+    return num_places(begin_bit, end_bit, kDigits[i % kNumDigits]) <= kMaxPlaces;
+  };
+  const int count = num_shapes * kNumLimits * kNumDigits;
   g_error[0] = '\0';
   if (temp_bytes == nullptr) return fail(ONESWEEP_ERROR_INVALID_VALUE, "temp_bytes is NULL");
   if (d_temp != nullptr && cfg_out == nullptr)
@@ -1168,6 +1225,7 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "repetitions %d not in [1, 100]", repetitions);
   size_t need = 0;
   for (int i = 0; i < count; ++i) {
+    if (!applies(i)) continue;
     onesweep_config_t c = candidate(i);
     size_t sz = 0;
     onesweep_status_t st = onesweep_sort_segments(nullptr, &sz, d_keys_in, d_keys_out, d_vals_in,
@@ -1195,6 +1253,7 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
   float best_ms = 0.0f;
   int best = -1;
   for (int i = 0; i < count && st == ONESWEEP_SUCCESS; ++i) {
+    if (!applies(i)) continue;
     onesweep_config_t c = candidate(i);
     size_t sz = *temp_bytes;
     auto run = [&]() {

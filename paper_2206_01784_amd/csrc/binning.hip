@@ -92,7 +92,7 @@ template <typename K, bool kOrdered, int kBlock>
 __device__ void count_segment_tile(const K *__restrict__ keys, const uint4 info,
                                    const SegmentTiles &seg, const KeyOrder &order,
                                    uint32_t *s_hist) {
-  constexpr int kMaxP = static_cast<int>(sizeof(K));
+  constexpr int kMaxP = kMaxPlaces;
   constexpr int kBatch = 8;  // independent loads in flight per thread
   const int tid = threadIdx.x;
   const int places = seg.places;
@@ -100,8 +100,8 @@ __device__ void count_segment_tile(const K *__restrict__ keys, const uint4 info,
   uint32_t masks[kMaxP];
 #pragma unroll
   for (int j = 0; j < kMaxP; ++j) {
-    const int lo = seg.begin_bit + j * kRadixBits;
-    const int hi = lo + kRadixBits < seg.end_bit ? lo + kRadixBits : seg.end_bit;
+    const int lo = seg.begin_bit + j * seg.digit_bits;
+    const int hi = lo + seg.digit_bits < seg.end_bit ? lo + seg.digit_bits : seg.end_bit;
     shifts[j] = j < places ? lo : 0;
     masks[j] = j < places ? ((1u << (hi - lo)) - 1u) : 0u;
   }
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(kBlock)
   constexpr size_t kRankBytes = sizeof(uint32_t) * kWaves * kRadix * kEntryWords;
   constexpr size_t kTileBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
   constexpr size_t kCountBytes =
-      kCounted ? sizeof(uint32_t) * sizeof(K) * kRadix * kSegCountCopies : 0;
+      kCounted ? sizeof(uint32_t) * kMaxPlaces * kRadix * kSegCountCopies : 0;
   constexpr size_t kStageBytes = kTileBytes > kCountBytes ? kTileBytes : kCountBytes;
   __shared__ __attribute__((aligned(16))) unsigned char s_stage[kStageBytes];
   __shared__ Idx s_gbase[kRadix];

@@ -12,7 +12,7 @@ namespace onesweep {
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;  // r = 256 bins per digit place
-constexpr int kMaxPlaces = 8;            // 64-bit keys with 8-bit digits
+constexpr int kMaxPlaces = 8;            // digit places of one sort (64-bit keys, 8-bit digits)
 constexpr int kWave = 64;
 
 // Chained-scan status word (Section 3, Figure 6): 2-bit status above a
@@ -82,6 +82,7 @@ struct SegmentTiles {
   const SegmentPlan *plan;
   int places;
   int begin_bit, end_bit;       // bit range of all places (the counting workgroups)
+  int digit_bits;               // width of a digit place (4..8)
 };
 
 // Idx is the type of element positions: uint32_t below 2^31 elements,
@@ -125,7 +126,8 @@ struct HistogramArgs {
   uint32_t n;
   int begin_bit;
   int end_bit;
-  int places;
+  int places;      // at most one per byte of the key in one launch
+  int digit_bits;  // width of a digit place (4..8)
   KeyOrder order;
 };
 

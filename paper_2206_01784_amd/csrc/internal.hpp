@@ -86,12 +86,13 @@ hipError_t launch_upsweep(int key_bits, int block, int ipt, const void *args, ui
 hipError_t launch_tile_scan(uint32_t *counts, uint32_t tiles, const PassPlan *plan, int place,
                             hipStream_t stream);
 
-// Histogram of all places (phase 1), persistent tile-cyclic grid, over
-// n < 2^31 keys; the counts are added to hist, or to the 64-bit hist64 when it
-// is not NULL (larger sorts histogram portions of the keys into it).
+// Histogram of the places of [begin_bit, end_bit) (phase 1), digit_bits
+// wide, at most key_bits / 8 places per launch, persistent tile-cyclic grid,
+// over n < 2^31 keys; the counts are added to hist, or to the 64-bit hist64
+// when it is not NULL (larger sorts histogram portions of the keys into it).
 hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist,
                             unsigned long long *hist64, uint32_t n, int begin_bit, int end_bit,
-                            int places, const KeyOrder &order, uint32_t grid,
+                            int places, int digit_bits, const KeyOrder &order, uint32_t grid,
                             hipStream_t stream);
 
 // Exclusive sums of every place's histogram and the pass plan (phase 2):
@@ -169,6 +170,7 @@ struct LdsSortArgs {
   int begin_bit;
   int end_bit;
   int places;
+  int digit_bits;
   KeyOrder order;
 };
 int lds_class_capacity(int cls);

@@ -127,17 +127,17 @@ hipError_t launch_infer(const InferArgs &a, hipStream_t stream) {
 
 // ---------------------------------------------------------------- selection
 // Features and the forward pass of one input fused into one workgroup of
-// 1024 threads, everything staged in LDS: the parameters (70 KB, coalesced
-// loads issued together with the key samples), the sampled digit counts, and
-// each layer's activations. Dot products are split over groups of threads
-// whose lanes read consecutive weights; partial sums meet in LDS. The result
-// (outputs and the chosen class) equals infer_kernel's up to float32
-// summation order.
+// 1024 threads: the sampled digit counts and each layer's activations in
+// LDS, the parameters read from global memory (70 KB, cached; the learned
+// sort runs this kernel beside the histogram, whose LDS atomics would slow
+// a copy of the parameters in LDS several times over). Dot products are
+// split over groups of threads whose lanes read consecutive weights; partial
+// sums meet in LDS. The result (outputs and the chosen class) equals
+// infer_kernel's up to float32 summation order.
 template <typename K>
 __global__ void __launch_bounds__(1024) select_kernel(SelectArgs a) {
   constexpr int kThreads = 1024;
   constexpr int kEncOut = kMlpPlaces * kMlpEnc;  // 128
-  __shared__ float s_p[kMlpParams];
   __shared__ uint32_t s_hist[kMlpPlaces * kRadix];
   __shared__ float s_part[kThreads];
   __shared__ float s_u[kMlpU];
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(1024) select_kernel(SelectArgs a) {
   const int tid = threadIdx.x;
   const K *keys = static_cast<const K *>(a.keys);
   for (int i = tid; i < kMlpPlaces * kRadix; i += kThreads) s_hist[i] = 0u;
-  for (int i = tid; i < kMlpParams; i += kThreads) s_p[i] = a.params[i];
+  const float *__restrict__ params = a.params;
   const uint64_t n = a.n;
   const uint32_t m = n < kMlpSamples ? static_cast<uint32_t>(n) : kMlpSamples;
   K k[kMlpSamples / kThreads];
@@ -168,8 +168,9 @@ __global__ void __launch_bounds__(1024) select_kernel(SelectArgs a) {
     }
   }
   __syncthreads();
-  const float *We = s_p + kOffWe, *be = s_p + kOffBe, *W1 = s_p + kOffW1, *b1 = s_p + kOffB1;
-  const float *W2 = s_p + kOffW2, *b2 = s_p + kOffB2, *W3 = s_p + kOffW3, *b3 = s_p + kOffB3;
+  const float *We = params + kOffWe, *be = params + kOffBe, *W1 = params + kOffW1;
+  const float *b1 = params + kOffB1, *W2 = params + kOffW2, *b2 = params + kOffB2;
+  const float *W3 = params + kOffW3, *b3 = params + kOffB3;
   const float fm = static_cast<float>(m);
   {
     // encoder: output o = (place o / 16, unit o % 16), 8 parts of 32 bins

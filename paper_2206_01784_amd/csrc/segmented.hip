@@ -256,8 +256,8 @@ __global__ void __launch_bounds__(kBlock)
       if constexpr (kVals) val[i] = q < len ? a.vals_in[lo + q] : 0u;
     }
     for (int j = 0; j < a.places; ++j) {
-      const int shift = a.begin_bit + j * kRadixBits;
-      const int width = min(kRadixBits, a.end_bit - shift);
+      const int shift = a.begin_bit + j * a.digit_bits;
+      const int width = min(a.digit_bits, a.end_bit - shift);
       const uint32_t mask = (1u << width) - 1u;
       uint32_t pos[kIpt];
 #pragma unroll

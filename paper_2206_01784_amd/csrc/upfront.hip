@@ -20,7 +20,7 @@ namespace onesweep {
 // 64 / kCopies-way.
 template <typename K, int kBlock, int kVec, int kCopies, bool kOrdered>
 __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
-  constexpr int kMaxP = static_cast<int>(sizeof(K));  // 8-bit places in the key
+  constexpr int kMaxP = static_cast<int>(sizeof(K));  // places one launch counts
   constexpr int kPerVec = 16 / static_cast<int>(sizeof(K));
   constexpr int kTile = kBlock * kVec * kPerVec;
   __shared__ uint32_t s_hist[kMaxP * kRadix * kCopies];
@@ -32,8 +32,8 @@ __global__ void __launch_bounds__(kBlock) histogram_kernel(HistogramArgs<K> a) {
   uint32_t masks[kMaxP];
 #pragma unroll
   for (int j = 0; j < kMaxP; ++j) {
-    const int lo = a.begin_bit + j * kRadixBits;
-    const int hi = min(lo + kRadixBits, a.end_bit);
+    const int lo = a.begin_bit + j * a.digit_bits;
+    const int hi = min(lo + a.digit_bits, a.end_bit);
     shifts[j] = lo < 64 ? lo : 0;
     masks[j] = (j < a.places) ? ((1u << (hi - lo)) - 1u) : 0u;
   }
@@ -153,11 +153,11 @@ constexpr int kHistCopies64 = 8;
 
 hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist,
                             unsigned long long *hist64, uint32_t n, int begin_bit, int end_bit,
-                            int places, const KeyOrder &order, uint32_t grid,
+                            int places, int digit_bits, const KeyOrder &order, uint32_t grid,
                             hipStream_t stream) {
   if (key_bits == 32) {
     HistogramArgs<uint32_t> a{static_cast<const uint32_t *>(keys), hist, hist64, n, begin_bit,
-                              end_bit, places, order};
+                              end_bit, places, digit_bits, order};
     if (key_order_is_plain(order))
       hipLaunchKernelGGL((histogram_kernel<uint32_t, kHistBlock, kHistVec, kHistCopies32, false>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
@@ -166,7 +166,7 @@ hipError_t launch_histogram(int key_bits, const void *keys, uint32_t *hist,
                          dim3(grid), dim3(kHistBlock), 0, stream, a);
   } else {
     HistogramArgs<uint64_t> a{static_cast<const uint64_t *>(keys), hist, hist64, n, begin_bit,
-                              end_bit, places, order};
+                              end_bit, places, digit_bits, order};
     if (key_order_is_plain(order))
       hipLaunchKernelGGL((histogram_kernel<uint64_t, kHistBlock, kHistVec, kHistCopies64, false>),
                          dim3(grid), dim3(kHistBlock), 0, stream, a);

@@ -76,10 +76,18 @@ def test_unsupported_config_is_rejected():
                                 ctypes.byref(cfg), None)
     assert rc == ow.ERROR_UNSUPPORTED
     assert ow.tile_items(32, False, cfg) == 0
-    cfg = ow.make_config(digit_bits=7)
-    rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, 32, 0, 32, 1,
-                                ctypes.byref(cfg), None)
-    assert rc == ow.ERROR_UNSUPPORTED
+    # digit widths 4..8 are built; a sort covers at most 8 places
+    for d, kb, end, code in ((3, 32, 32, ow.ERROR_UNSUPPORTED), (9, 32, 32, ow.ERROR_UNSUPPORTED),
+                             (7, 64, 64, ow.ERROR_UNSUPPORTED), (7, 64, 56, 0),
+                             (4, 32, 32, 0), (8, 64, 64, 0)):
+        cfg = ow.make_config(digit_bits=d)
+        rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 100, kb, 0, end, 1,
+                                    ctypes.byref(cfg), None)
+        assert rc == code, (d, kb, end)
+    # narrower digits: more places, so more status words per sort
+    n = 1 << 24
+    assert ow.sort_temp_bytes(n, 32, config=ow.make_config(digit_bits=6)) > \
+        ow.sort_temp_bytes(n, 32)
 
 
 def test_reduce_then_scan_config_validation_needs_no_gpu():
