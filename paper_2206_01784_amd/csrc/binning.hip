@@ -347,8 +347,7 @@ __global__ void __launch_bounds__(kBlock)
   // loads are unconditional (lanes past the end load the tile's last key,
   // in bounds, and take the padding only when ranked), so no branch
   // separates the loads from the ranking and each batch waits only for its
-  // own load; pairs load in two branches, which needs fewer registers where
-  // their values are live.
+  // own load; pairs load in two branches.
   K key[kIpt];
   const Idx wave_base = tile_base + static_cast<uint32_t>(wave * kWaveItems + lane);
   const K pad = kOrdered ? static_cast<K>(a.order.pad) : static_cast<K>(~K(0));
@@ -524,15 +523,26 @@ __global__ void __launch_bounds__(kBlock)
     for (int i = 0; i < kIpt; ++i) s_keys[pos.get(i)] = key[i];
   }
 
+  // Values are loaded only once the keys have been written out: loaded
+  // before the look-back they were held in registers across it and the key
+  // scatter, which spilled (1024 x 16 pairs: 1173 -> 1086 us per pass at
+  // 2^28 with the late loads; 64-bit pairs 854 -> 821 us at 2^27). The
+  // segmented launch that also counts loads them early: its counting and
+  // wait code leave the late loads spilling there (233 against 207 us at
+  // 1024 x 16 on 20000 segments of 2^26 pairs).
+  constexpr bool kLateVals = !kCounted;
   uint32_t val[kVals ? kIpt : 1];
-  if constexpr (kVals) {
-    const uint32_t *__restrict__ vsrc = a.vals[src_id];
+  auto load_vals = [&]() {
+    if constexpr (kVals) {
+      const uint32_t *__restrict__ vsrc = a.vals[src_id];
 #pragma unroll
-    for (int i = 0; i < kIpt; ++i) {
-      const Idx idx = wave_base + static_cast<uint32_t>(i * kWave);
-      val[i] = (full || idx < tile_end) ? vsrc[idx] : 0u;
+      for (int i = 0; i < kIpt; ++i) {
+        const Idx idx = wave_base + static_cast<uint32_t>(i * kWave);
+        val[i] = (full || idx < tile_end) ? vsrc[idx] : 0u;
+      }
     }
-  }
+  };
+  if constexpr (!kLateVals) load_vals();
 
   // 4b. Decoupled look-back: thread v sums the counts of earlier tiles for
   // digit v, walking backwards until it meets an inclusive prefix. Each round
@@ -597,6 +607,7 @@ __global__ void __launch_bounds__(kBlock)
   // 5b'. Short-circuit: every key of a one-digit tile goes to its bin at its
   // input position, straight from registers.
   if (uniform != 0u) {
+    if constexpr (kLateVals) load_vals();
     const Idx g0 = s_gbase[uniform - 1u] + static_cast<uint32_t>(wave * kWaveItems + lane);
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
@@ -647,6 +658,7 @@ __global__ void __launch_bounds__(kBlock)
   // 5c. Values follow their keys through the same LDS positions.
   if constexpr (kVals) {
     uint32_t *__restrict__ vdst = a.vals[dst_id];
+    if constexpr (kLateVals) load_vals();
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) s_vals[pos.get(i)] = val[i];
@@ -807,7 +819,7 @@ __global__ void __launch_bounds__(kBlock)
 // more: the default large-input shape of each key width and value presence.
 #define ONESWEEP_WIDE_SHAPES(X)   \
   X(uint32_t, false, 1024, 19, 0) \
-  X(uint32_t, true, 1024, 18, 0)  \
+  X(uint32_t, true, 1024, 16, 0)  \
   X(uint64_t, false, 1024, 9, 0)  \
   X(uint64_t, true, 1024, 9, 0)
 
@@ -849,9 +861,8 @@ size_t binning_tile_items(const BinningShape &s) {
 // 2^23 (2^28: 2.45 against 2.58 with 1024 x 16 and 2.95 with 1024 x 11).
 // 32-bit pairs: 1024 x 11 from 2^21 (the sweep: 8% faster than 1024 x 8
 // between 2^21 and 2^22), 1024 x 16 from 2^22 (2^26: 1.23 against 1.29 with
-// 1024 x 11 and 1.27 with 1024 x 18), 1024 x 18 from 2^28 (4.84 against
-// 4.96 with 1024 x 16; it spills a few registers, which costs more than the
-// larger tile saves below 2^28). 64-bit keys 1024 x 9 (3% faster than
+// 1024 x 11 and 1.27 with 1024 x 18; at 2^28 a pass takes 1086 us, as with
+// 1024 x 18, which spills a few registers). 64-bit keys 1024 x 9 (3% faster than
 // 1024 x 8); 64-bit pairs 1024 x 9 from 2^21 (the sweep: 1-2% faster than
 // 1024 x 8 at every size from 2^21 to 2^28).
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
@@ -865,8 +876,7 @@ BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
   if (n < (size_t(1) << 21)) return BinningShape{32, has_values, 1024, 8, kRankBallot};
   if (has_values) {
     if (n < (size_t(1) << 22)) return BinningShape{32, true, 1024, 11, kRankBallot};
-    if (n < (size_t(1) << 28)) return BinningShape{32, true, 1024, 16, kRankBallot};
-    return BinningShape{32, true, 1024, 18, kRankBallot};
+    return BinningShape{32, true, 1024, 16, kRankBallot};
   }
   if (n < (size_t(3) << 20)) return BinningShape{32, false, 1024, 11, kRankBallot};
   if (n < (size_t(1) << 23)) return BinningShape{32, false, 1024, 16, kRankBallot};
