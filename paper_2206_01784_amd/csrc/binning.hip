@@ -193,7 +193,14 @@ __global__ void __launch_bounds__(kBlock)
   // LDS), and 64-bit pairs would spill holding their keys across the
   // look-back.
   constexpr bool kShortCircuit = sizeof(K) == 4 && kVals;
-  constexpr size_t kKeyBytes = sizeof(K) * kTile;
+  // 64-bit keys without values regroup their two 32-bit halves one after
+  // the other through a 4-byte-per-key buffer, so the tile needs half the
+  // LDS and 1024 x 14 tiles keep two workgroups per CU (1024 x 9 at most
+  // with 8 bytes per key): 2^27 keys, 548 -> 513 us per pass; the second
+  // round trip costs nothing measurable at equal tiles (548 against 547 us
+  // at 1024 x 9).
+  constexpr bool kSplit = sizeof(K) == 8 && !kVals;
+  constexpr size_t kKeyBytes = (kSplit ? 4 : sizeof(K)) * kTile;
   constexpr size_t kRankBytes = sizeof(uint32_t) * kWaves * kRadix * kEntryWords;
   constexpr size_t kTileBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
   constexpr size_t kCountBytes =
@@ -518,7 +525,16 @@ __global__ void __launch_bounds__(kBlock)
 
   // 5a. Regroup the keys by digit in LDS (not needed when the tile has one
   // digit: its sorted order is its input order).
-  if (uniform == 0u) {
+  // (Split keys: the low halves now, the high halves after the look-back.)
+  uint32_t key_hi[kSplit ? kIpt : 1];
+  uint32_t *s_half = reinterpret_cast<uint32_t *>(s_stage);
+  if constexpr (kSplit) {
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+      s_half[pos.get(i)] = static_cast<uint32_t>(key[i]);
+      key_hi[i] = static_cast<uint32_t>(key[i] >> 32);
+    }
+  } else if (uniform == 0u) {
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) s_keys[pos.get(i)] = key[i];
   }
@@ -630,11 +646,26 @@ __global__ void __launch_bounds__(kBlock)
   // latencies overlap instead of alternating with the stores (pairs hold
   // their values in registers here and would spill).
   Idx dst_idx[kVals ? kIpt : 1];
+  uint32_t lo_half[kSplit ? kIpt : 1];
+  if constexpr (kSplit) {  // slot-order low halves, then the high halves
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) lo_half[i] = s_half[i * kBlock + tid];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) s_half[pos.get(i)] = key_hi[i];
+    __syncthreads();
+  }
+  auto slot_key = [&](int i, uint32_t q) -> K {  // the key at tile position q
+    if constexpr (kSplit)
+      return static_cast<K>((static_cast<uint64_t>(s_half[q]) << 32) | lo_half[i]);
+    else
+      return s_keys[q];
+  };
   if (!kVals && full) {
     K k[kIpt];
     Idx g[kIpt];
 #pragma unroll
-    for (int i = 0; i < kIpt; ++i) k[i] = s_keys[i * kBlock + tid];
+    for (int i = 0; i < kIpt; ++i) k[i] = slot_key(i, i * kBlock + tid);
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) g[i] = s_gbase[digit(k[i])] + static_cast<uint32_t>(i * kBlock + tid);
 #pragma unroll
@@ -647,7 +678,7 @@ __global__ void __launch_bounds__(kBlock)
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t q = i * kBlock + tid;
       if (q < tile_count) {
-        const K k = s_keys[q];
+        const K k = slot_key(i, q);
         const Idx g = s_gbase[digit(k)] + q;
         if (!kCheckedStores || g < n) dst[g] = k;
         if constexpr (kVals) dst_idx[i] = g;
@@ -675,6 +706,12 @@ __global__ void __launch_bounds__(kBlock)
 // Instantiated shapes: (key type, values, workgroup size, items per thread,
 // rank algorithm).
 #define ONESWEEP_BINNING_SHAPES(X)    \
+  X(uint64_t, false, 1024, 12, 0)     \
+  X(uint64_t, false, 1024, 14, 0)     \
+  X(uint64_t, false, 1024, 14, 1)     \
+  X(uint64_t, false, 1024, 14, 2)     \
+  X(uint64_t, true, 1024, 12, 0)      \
+  X(uint64_t, true, 1024, 14, 0)      \
   X(uint32_t, false, 1024, 16, 0)     \
   X(uint32_t, false, 1024, 18, 0)     \
   X(uint32_t, false, 1024, 19, 0)     \
@@ -792,6 +829,8 @@ __global__ void __launch_bounds__(kBlock)
 // Shapes built for the reduce-then-scan baseline (ballot ranking): the
 // default shapes of every key width and value presence.
 #define ONESWEEP_DOWNSWEEP_SHAPES(X) \
+  X(uint64_t, false, 1024, 12, 0)    \
+  X(uint64_t, false, 1024, 14, 0)    \
   X(uint32_t, false, 1024, 16, 0)    \
   X(uint32_t, true, 1024, 16, 0)     \
   X(uint32_t, false, 1024, 18, 0)    \
@@ -820,7 +859,7 @@ __global__ void __launch_bounds__(kBlock)
 #define ONESWEEP_WIDE_SHAPES(X)   \
   X(uint32_t, false, 1024, 19, 0) \
   X(uint32_t, true, 1024, 16, 0)  \
-  X(uint64_t, false, 1024, 9, 0)  \
+  X(uint64_t, false, 1024, 14, 0) \
   X(uint64_t, true, 1024, 9, 0)
 
 #define ONESWEEP_SHAPE_IS(K, V, B, I, R) \
@@ -862,13 +901,17 @@ size_t binning_tile_items(const BinningShape &s) {
 // 32-bit pairs: 1024 x 11 from 2^21 (the sweep: 8% faster than 1024 x 8
 // between 2^21 and 2^22), 1024 x 16 from 2^22 (2^26: 1.23 against 1.29 with
 // 1024 x 11 and 1.27 with 1024 x 18; at 2^28 a pass takes 1086 us, as with
-// 1024 x 18, which spills a few registers). 64-bit keys 1024 x 9 (3% faster than
-// 1024 x 8); 64-bit pairs 1024 x 9 from 2^21 (the sweep: 1-2% faster than
-// 1024 x 8 at every size from 2^21 to 2^28).
+// 1024 x 18, which spills a few registers). 64-bit keys, regrouped in two
+// 32-bit halves: 1024 x 9 from 2^21, 1024 x 12 from 2^22 and 1024 x 14 from
+// 2^26 (2^27: 4.36 ms against 4.41 with 1024 x 12 and 4.66 with 1024 x 9);
+// 64-bit pairs 1024 x 9 from 2^21 (the sweep: 1-2% faster than 1024 x 8 at
+// every size from 2^21 to 2^28).
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
   if (key_bits == 64) {
     if (has_values && n < (size_t(3) << 16)) return BinningShape{64, true, 256, 8, kRankBallot};
     if (n < (size_t(1) << 19)) return BinningShape{64, has_values, 512, 8, kRankBallot};
+    if (n >= (size_t(1) << 26) && !has_values) return BinningShape{64, false, 1024, 14, kRankBallot};
+    if (n >= (size_t(1) << 22) && !has_values) return BinningShape{64, false, 1024, 12, kRankBallot};
     if (n >= (size_t(1) << 21)) return BinningShape{64, has_values, 1024, 9, kRankBallot};
     return BinningShape{64, has_values, 1024, 8, kRankBallot};
   }

@@ -136,6 +136,8 @@ __global__ void __launch_bounds__(kTileScanBlock)
   X(uint32_t, 1024, 18)            \
   X(uint32_t, 1024, 19)            \
   X(uint64_t, 1024, 9)             \
+  X(uint64_t, 1024, 12)            \
+  X(uint64_t, 1024, 14)            \
   X(uint64_t, 256, 8)              \
   X(uint64_t, 512, 8)              \
   X(uint64_t, 1024, 8)

@@ -23,7 +23,7 @@ SHAPES = {
                   (1024, 19)],
     (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11),
                  (1024, 18)],
-    (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
+    (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9), (1024, 14)],
     (64, True): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
 }
 

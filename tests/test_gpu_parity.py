@@ -96,7 +96,7 @@ SHAPES = {
                   (1024, 19)],
     (32, True): [(256, 8), (256, 16), (512, 16), (512, 12), (1024, 8), (1024, 10), (1024, 11),
                  (1024, 18)],
-    (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
+    (64, False): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9), (1024, 14)],
     (64, True): [(256, 8), (256, 16), (512, 8), (512, 12), (1024, 8), (1024, 9)],
 }
 RANKS = (1, 2, 3)  # one ballot per digit bit; LDS presence masks; ballots + LDS atomics
@@ -182,26 +182,29 @@ def check_sort(ow, keys, vals, begin, end, cfg=None, inplace=False):
         assert np.array_equal(got_v, wv)
 
 
-# Tile shapes built with ballot ranking only: the large-input defaults of the
-# other value presence (32-bit keys 1024 x 16 and 1024 x 18, pairs 1024 x 16
-# and 1024 x 19), so that every learned-selector class serves keys and pairs.
-BALLOT_ONLY_SHAPES = {False: [(1024, 16), (1024, 18)], True: [(1024, 16), (1024, 19)]}
+# Tile shapes built with ballot ranking only: large-input shapes of one
+# value presence also built for the other (32-bit keys 1024 x 16 and
+# 1024 x 18, 32-bit pairs 1024 x 16 and 1024 x 19, 64-bit keys 1024 x 12,
+# 64-bit pairs 1024 x 12 and 1024 x 14), so that every learned-selector
+# class serves keys and pairs.
+BALLOT_ONLY_SHAPES = {(32, False): [(1024, 16), (1024, 18)], (32, True): [(1024, 16), (1024, 19)],
+                      (64, False): [(1024, 12)], (64, True): [(1024, 12), (1024, 14)]}
 
 
-@pytest.mark.parametrize("vals", [False, True])
-def test_ballot_only_shapes(ow, vals):
-    for block, ipt in BALLOT_ONLY_SHAPES[vals]:
+@pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
+def test_ballot_only_shapes(ow, kb, vals):
+    for block, ipt in BALLOT_ONLY_SHAPES[(kb, vals)]:
         cfg = ow.make_config(block_threads=block, items_per_thread=ipt, rank_algorithm=1)
-        T = ow.tile_items(32, vals, cfg)
+        T = ow.tile_items(kb, vals, cfg)
         assert T == block * ipt
         for n in (2, T - 1, T + 1, 7 * T + 333):
-            keys = W.uniform(17 + n % 13, n, 32)
+            keys = W.uniform(17 + n % 13, n, kb)
             v = np.arange(n, dtype=np.uint32) if vals else None
-            check_sort(ow, keys, v, 0, 32, cfg)
+            check_sort(ow, keys, v, 0, kb, cfg)
         n = 5 * T + 77
-        keys = W.uniform(23, n, 32)
+        keys = W.uniform(23, n, kb)
         v = np.arange(n, dtype=np.uint32) if vals else None
-        for shift, width in ((0, 8), (24, 8), (5, 3)):
+        for shift, width in ((0, 8), (kb - 8, 8), (5, 3)):
             off = oracle.exclusive_sums(oracle.histograms(keys, shift, shift + width, width))[0]
             off256 = np.full(256, n, dtype=np.uint32)
             off256[:off.size] = off
@@ -373,6 +376,16 @@ RTS_SHAPES = {
     32: [(256, 8), (512, 16), (1024, 8), (1024, 11), (1024, 16), (1024, 18), (1024, 19)],
     64: [(256, 8), (512, 8), (1024, 8), (1024, 9)],
 }
+
+
+def test_reduce_then_scan_64_bit_keys_large_tiles(ow):
+    """The baseline's 64-bit keys-only shapes of the default table from 2^22
+    keys (1024 x 12 and 1024 x 14, keys regrouped in two 32-bit halves)."""
+    for ipt in (12, 14):
+        cfg = ow.make_config(1024, ipt, algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)
+        T = ow.tile_items(64, False, cfg)
+        for n in (T - 1, 5 * T + 333):
+            check_sort(ow, W.uniform(31 + ipt, n, 64), None, 0, 64, cfg)
 
 
 @pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
