@@ -193,13 +193,13 @@ __global__ void __launch_bounds__(kBlock)
   // LDS), and 64-bit pairs would spill holding their keys across the
   // look-back.
   constexpr bool kShortCircuit = sizeof(K) == 4 && kVals;
-  // 64-bit keys without values regroup their two 32-bit halves one after
-  // the other through a 4-byte-per-key buffer, so the tile needs half the
-  // LDS and 1024 x 14 tiles keep two workgroups per CU (1024 x 9 at most
-  // with 8 bytes per key): 2^27 keys, 548 -> 513 us per pass; the second
-  // round trip costs nothing measurable at equal tiles (548 against 547 us
-  // at 1024 x 9).
-  constexpr bool kSplit = sizeof(K) == 8 && !kVals;
+  // 64-bit keys regroup their two 32-bit halves one after the other through
+  // a 4-byte-per-key buffer (values use the same buffer after them), so the
+  // tile needs half the LDS and 1024 x 14 tiles keep two workgroups per CU
+  // (1024 x 9 at most with 8 bytes per key): 2^27 keys, 548 -> 513 us per
+  // pass, 2^27 pairs 822 -> 774 us; the second round trip costs nothing
+  // measurable at equal tiles (548 against 547 us at 1024 x 9).
+  constexpr bool kSplit = sizeof(K) == 8;
   constexpr size_t kKeyBytes = (kSplit ? 4 : sizeof(K)) * kTile;
   constexpr size_t kRankBytes = sizeof(uint32_t) * kWaves * kRadix * kEntryWords;
   constexpr size_t kTileBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
@@ -831,6 +831,8 @@ __global__ void __launch_bounds__(kBlock)
 #define ONESWEEP_DOWNSWEEP_SHAPES(X) \
   X(uint64_t, false, 1024, 12, 0)    \
   X(uint64_t, false, 1024, 14, 0)    \
+  X(uint64_t, true, 1024, 12, 0)     \
+  X(uint64_t, true, 1024, 14, 0)     \
   X(uint32_t, false, 1024, 16, 0)    \
   X(uint32_t, true, 1024, 16, 0)     \
   X(uint32_t, false, 1024, 18, 0)    \
@@ -860,7 +862,7 @@ __global__ void __launch_bounds__(kBlock)
   X(uint32_t, false, 1024, 19, 0) \
   X(uint32_t, true, 1024, 16, 0)  \
   X(uint64_t, false, 1024, 14, 0) \
-  X(uint64_t, true, 1024, 9, 0)
+  X(uint64_t, true, 1024, 14, 0)
 
 #define ONESWEEP_SHAPE_IS(K, V, B, I, R) \
   (s.key_bits == 8 * (int)sizeof(K) && s.has_values == V && s.block == B && s.ipt == I && s.rank == R)
@@ -901,17 +903,17 @@ size_t binning_tile_items(const BinningShape &s) {
 // 32-bit pairs: 1024 x 11 from 2^21 (the sweep: 8% faster than 1024 x 8
 // between 2^21 and 2^22), 1024 x 16 from 2^22 (2^26: 1.23 against 1.29 with
 // 1024 x 11 and 1.27 with 1024 x 18; at 2^28 a pass takes 1086 us, as with
-// 1024 x 18, which spills a few registers). 64-bit keys, regrouped in two
-// 32-bit halves: 1024 x 9 from 2^21, 1024 x 12 from 2^22 and 1024 x 14 from
-// 2^26 (2^27: 4.36 ms against 4.41 with 1024 x 12 and 4.66 with 1024 x 9);
-// 64-bit pairs 1024 x 9 from 2^21 (the sweep: 1-2% faster than 1024 x 8 at
-// every size from 2^21 to 2^28).
+// 1024 x 18, which spills a few registers). 64-bit keys and pairs,
+// regrouped in two 32-bit halves: 1024 x 9 from 2^21 (64-bit pairs: 1-2%
+// faster than 1024 x 8 in the seeded sweep), 1024 x 12 from 2^22 and
+// 1024 x 14 from 2^26 (2^27 keys: 4.36 ms against 4.41 with 1024 x 12 and
+// 4.66 with 1024 x 9; a 2^27-pair pass 774 us against 784 and 822).
 BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
   if (key_bits == 64) {
     if (has_values && n < (size_t(3) << 16)) return BinningShape{64, true, 256, 8, kRankBallot};
     if (n < (size_t(1) << 19)) return BinningShape{64, has_values, 512, 8, kRankBallot};
-    if (n >= (size_t(1) << 26) && !has_values) return BinningShape{64, false, 1024, 14, kRankBallot};
-    if (n >= (size_t(1) << 22) && !has_values) return BinningShape{64, false, 1024, 12, kRankBallot};
+    if (n >= (size_t(1) << 26)) return BinningShape{64, has_values, 1024, 14, kRankBallot};
+    if (n >= (size_t(1) << 22)) return BinningShape{64, has_values, 1024, 12, kRankBallot};
     if (n >= (size_t(1) << 21)) return BinningShape{64, has_values, 1024, 9, kRankBallot};
     return BinningShape{64, has_values, 1024, 8, kRankBallot};
   }

@@ -374,18 +374,8 @@ def test_graph_capture_replays(ow):
 
 RTS_SHAPES = {
     32: [(256, 8), (512, 16), (1024, 8), (1024, 11), (1024, 16), (1024, 18), (1024, 19)],
-    64: [(256, 8), (512, 8), (1024, 8), (1024, 9)],
+    64: [(256, 8), (512, 8), (1024, 8), (1024, 9), (1024, 12), (1024, 14)],
 }
-
-
-def test_reduce_then_scan_64_bit_keys_large_tiles(ow):
-    """The baseline's 64-bit keys-only shapes of the default table from 2^22
-    keys (1024 x 12 and 1024 x 14, keys regrouped in two 32-bit halves)."""
-    for ipt in (12, 14):
-        cfg = ow.make_config(1024, ipt, algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)
-        T = ow.tile_items(64, False, cfg)
-        for n in (T - 1, 5 * T + 333):
-            check_sort(ow, W.uniform(31 + ipt, n, 64), None, 0, 64, cfg)
 
 
 @pytest.mark.parametrize("kb,vals", [(32, False), (32, True), (64, False), (64, True)])
