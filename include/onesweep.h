@@ -222,8 +222,8 @@ onesweep_status_t onesweep_sort_pairs(void *d_temp, size_t *temp_bytes, const vo
  * allocates nothing; it enqueues kernels only (graph-capturable).
  *  - Size limit: the temporary storage onesweep_sort_keys would need (its
  *    size query, which depends on n, key_bits, the bit range and cfg) must
- *    fit the array; with the default configuration that is about 15.4
- *    million 32-bit or 7.5 million 64-bit keys. Larger inputs return
+ *    fit the array; with the default configuration that is about 15.9
+ *    million 32-bit or 7.7 million 64-bit keys. Larger inputs return
  *    ONESWEEP_ERROR_TOO_LARGE before anything is enqueued.
  *  - The first call on a device looks up the array's device address
  *    (hipGetSymbolAddress, which may load the library's code on that
