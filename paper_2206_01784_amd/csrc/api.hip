@@ -1184,7 +1184,8 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
   // path.
   static const int kShapes32[][2] = {{256, 8},  {256, 16},  {512, 16},
                                      {1024, 8}, {1024, 11}, {1024, 16}};
-  static const int kShapes64[][2] = {{256, 8}, {256, 16}, {512, 8}, {1024, 8}, {1024, 9}};
+  static const int kShapes64[][2] = {{256, 8},  {256, 16}, {512, 8},
+                                     {1024, 8}, {1024, 9}, {1024, 14}};
   static const int kLimits[][3] = {{0, 0, 0},   {0, 0, 4096},  {0, 0, 2048}, {0, 0, -1},
                                    {0, -1, 0},  {-1, 0, 0},    {256, 1024, 4096}};
   // Digit widths: 8 bits, and 7 (one more place for 32-bit keys, fewer

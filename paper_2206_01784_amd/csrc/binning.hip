@@ -824,7 +824,9 @@ __global__ void __launch_bounds__(kBlock)
   X(uint32_t, false, 1024, 16, 0)          \
   X(uint32_t, true, 1024, 16, 0)           \
   X(uint64_t, false, 1024, 9, 0)           \
-  X(uint64_t, true, 1024, 9, 0)
+  X(uint64_t, true, 1024, 9, 0)            \
+  X(uint64_t, false, 1024, 14, 0)          \
+  X(uint64_t, true, 1024, 14, 0)
 
 // Shapes built for the reduce-then-scan baseline (ballot ranking): the
 // default shapes of every key width and value presence.
@@ -933,11 +935,12 @@ BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
 // eager, two streams; ms per sort): 32-bit keys 512 x 16 (0.79, against
 // 0.79 with 1024 x 16, 0.82 with 1024 x 11 and 0.96 with 256 x 16), 32-bit
 // pairs 1024 x 16 (1.01, against 1.06 with 1024 x 11 and 1.13 with
-// 512 x 16; 1.09 against 1.17 under graph replay), 64-bit keys 1024 x 9
-// (2.20 against 2.25 with 1024 x 8), 64-bit pairs 1024 x 9 (3.03 against
-// 3.09 with 1024 x 8).
+// 512 x 16; 1.09 against 1.17 under graph replay), 64-bit keys and pairs
+// 1024 x 14 with their keys regrouped in two halves (keys 1.86 against 1.90
+// with 1024 x 9 and 2.25 with 1024 x 8; pairs 2.50 against 2.61 with
+// 1024 x 9 and 3.09 with 1024 x 8).
 BinningShape segment_default_shape(int key_bits, bool has_values) {
-  if (key_bits == 64) return BinningShape{64, has_values, 1024, 9, kRankBallot};
+  if (key_bits == 64) return BinningShape{64, has_values, 1024, 14, kRankBallot};
   return has_values ? BinningShape{32, true, 1024, 16, kRankBallot}
                     : BinningShape{32, false, 512, 16, kRankBallot};
 }

@@ -132,7 +132,7 @@ def test_segments_one_stream_and_two_streams_agree(ow, kb):
 @pytest.mark.parametrize("kb,shape", [(32, (256, 8)), (32, (256, 16)), (32, (512, 16)),
                                       (32, (1024, 8)), (32, (1024, 11)), (32, (1024, 16)),
                                       (64, (256, 8)), (64, (512, 8)), (64, (256, 16)),
-                                      (64, (1024, 9))])
+                                      (64, (1024, 9)), (64, (1024, 14))])
 def test_segments_class_limits_and_tiles(ow, limits, kb, shape):
     cfg = ow.make_config(block_threads=shape[0], items_per_thread=shape[1],
                          segment_limits=limits)
