@@ -112,8 +112,8 @@ def test_full_segments_lognormal_20000(ow):
 
 
 def test_full_keys_beyond_2p30(ow):
-    """2^30 + 4097 uint32 keys: with the default 1024 x 11 tiles and strips of
-    at most 2^29 keys, each binning pass runs three strips (47,662 + 47,662
+    """2^30 + 4097 uint32 keys: with the default 1024 x 19 tiles and strips of
+    at most 2^29 keys, each binning pass runs three strips (27,594 + 27,594
     tiles and a last one-tile strip), each its own chained scan, the bin
     starts carried from strip to strip; bit-exact against the oracle."""
     n = (1 << 30) + 4097
