@@ -224,9 +224,15 @@ __global__ void __launch_bounds__(kBlock)
   const int width = a.width;
   const uint32_t mask = (1u << width) - 1u;
   const Idx n = a.n;
+  // 32-bit keys: one bit-field extract (the shift and width are uniform; the
+  // compiler keeps one of them in a vector register for the whole tile).
   auto digit = [&](K k) -> uint32_t {
-    if constexpr (kOrdered) return digit_of(k, shift, mask, a.order);
-    else return digit_of(k, shift, mask);
+    const K t = kOrdered ? ordered_bits(k, a.order) : k;
+    if constexpr (sizeof(K) == 4)
+      return __builtin_amdgcn_ubfe(static_cast<uint32_t>(t), static_cast<uint32_t>(shift),
+                                   static_cast<uint32_t>(width));
+    else
+      return digit_of(t, shift, mask);
   };
 
   // The segmented grid is sized for the most tiles the offsets could need;
