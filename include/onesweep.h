@@ -37,14 +37,18 @@
  *    very large problems"): one chained scan covers fewer than 2^30 keys.
  *    Whole plain sorts (onesweep_sort_keys/pairs) bin large inputs in strips
  *    of at most 2^29 keys, each its own chained scan whose last tile hands
- *    the next strip its bin starts. From 2^31 elements on they also keep
- *    64-bit histogram counts (the upfront histogram runs over portions of at
- *    most 2^30 keys), 64-bit bin starts and 64-bit element positions, as
- *    that section describes, and accept n below 2^36; at those sizes only
+ *    the next strip its bin starts. From 2^31 elements on, and where the
+ *    keys take more than 4 GiB (32-bit keys from 2^30 + 1, 64-bit keys from
+ *    2^29 + 1: below that, positions are stored through buffer resources,
+ *    whose offsets are 32-bit), they also keep 64-bit histogram counts (the
+ *    upfront histogram runs over portions of at most 2^30 keys), 64-bit bin
+ *    starts and 64-bit element positions, as that section describes, and
+ *    accept n below 2^36; at those sizes only
  *    the default tile shape of each key width and value presence is built
  *    (other tile configurations return ONESWEEP_ERROR_UNSUPPORTED) and the
  *    reduce-then-scan baseline is not. The other entry points accept n
- *    below 2^30. Larger n returns ONESWEEP_ERROR_TOO_LARGE.
+ *    below 2^30 (onesweep_binning_pass also at most 4 GiB of keys: 64-bit
+ *    keys up to 2^29). Larger n returns ONESWEEP_ERROR_TOO_LARGE.
  *  - Errors are returned as status codes; nothing is enqueued when argument
  *    validation fails. onesweep_last_error() describes the last failure of
  *    the calling thread.
@@ -261,9 +265,12 @@ onesweep_status_t onesweep_histogram(const void *d_keys, size_t n, int key_bits,
  * the exclusive sum of the digit counts. 1 <= width <= 8,
  * shift + width <= key_bits. src and dst must not overlap.
  * Temp layout (documented so tests can read the chained-scan state): bytes
- * [0, 256) hold the tile counter (uint32 0) and the look-back error word
- * (uint32 1: 0, or 1 when a tile gave up waiting, see
- * onesweep_config_t.lookback_spin_limit), then ceil(n / T) rows of 256 uint32
+ * [0, 256) hold the tile counter (uint32 0) and the error word (uint32 1:
+ * bit 0 set when a tile gave up waiting, see
+ * onesweep_config_t.lookback_spin_limit; bit 1 set when a tile found the
+ * destination run of one of its digits outside [0, n), from offsets that do
+ * not match the keys' digit counts: that tile writes nothing), then
+ * ceil(n / T) rows of 256 uint32
  * status words (row = tile, column = digit; Figure 6 layout: 2-bit status
  * above a 30-bit value). After a pass without look-back error every word
  * holds status G (2) and the tile's inclusive prefix count.

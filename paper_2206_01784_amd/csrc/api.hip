@@ -47,6 +47,13 @@ constexpr size_t kMaxN = size_t(1) << 30;  // 30-bit status values, one chained 
 // 2^36 elements (256 GiB of 32-bit keys) is beyond one GPU's memory.
 constexpr size_t kWideN = size_t(1) << 31;
 constexpr size_t kMaxSortN = size_t(1) << 36;
+// The 32-bit-position binning kernels store through buffer resources, whose
+// offsets are 32-bit: a sort whose key output passes 4 GiB (32-bit keys from
+// 2^30 on, 64-bit keys from 2^29) takes the 64-bit-position path too.
+constexpr size_t kBufferBytes = size_t(1) << 32;
+inline bool wide_positions(size_t n, int key_bits) {
+  return n >= kWideN || n * static_cast<size_t>(key_bits / 8) > kBufferBytes;
+}
 constexpr size_t kHistPortion = size_t(1) << 30;
 // A late tile choice (the learned selector) applies to at most 2^28 keys:
 // then every tile of at most 65536 keys bins each place in one strip, so
@@ -184,10 +191,10 @@ onesweep_status_t resolve(int key_bits, bool has_values, size_t n, const oneswee
   }
   const bool rts = r->algorithm == ONESWEEP_ALGORITHM_REDUCE_THEN_SCAN;
   const int mode = caller == kCallSegments ? kBinSegmented : (rts ? kBinDownsweep : kBinChained);
-  const bool wide = caller == kCallSort && n >= kWideN;
+  const bool wide = caller == kCallSort && wide_positions(n, key_bits);
   if (wide && rts)
     return fail(ONESWEEP_ERROR_UNSUPPORTED,
-                "reduce-then-scan is built for n below 2^31 (n = %zu)", n);
+                "reduce-then-scan is built for key outputs of at most 4 GiB (n = %zu)", n);
   if (!binning_shape_supported(r->shape, mode, wide) ||
       (rts && !upsweep_shape_supported(key_bits, r->shape.block, r->shape.ipt)))
     return fail(ONESWEEP_ERROR_UNSUPPORTED,
@@ -224,7 +231,7 @@ SortLayout sort_layout(size_t n, int key_bits, bool has_values, int places, size
                        bool late_status = false) {
   SortLayout L{};
   L.tiles_for_layout = tile;
-  const size_t cw = n >= kWideN ? 8 : 4;  // bytes of a count, offset or bin start
+  const size_t cw = wide_positions(n, key_bits) ? 8 : 4;  // bytes of a count, offset or bin start
   L.tiles = static_cast<uint32_t>((n + tile - 1) / tile);
   L.status_words_per_place = static_cast<size_t>(L.tiles) * kRadix;
   L.strip_tiles = static_cast<uint32_t>(std::max<size_t>(1, (size_t(1) << strip_log2) / tile));
@@ -407,8 +414,9 @@ onesweep_status_t sort_impl(void *d_temp, size_t *temp_bytes, const void *keys_i
     return ONESWEEP_SUCCESS;
   }
 
-  // Sorts of 2^31 elements or more keep 64-bit counts and bin offsets.
-  const bool wide = n >= kWideN;
+  // Sorts of 2^31 elements or more, or of more than 4 GiB of keys, keep
+  // 64-bit counts, bin offsets and positions.
+  const bool wide = wide_positions(n, key_bits);
   uint32_t *hist = wide ? nullptr : reinterpret_cast<uint32_t *>(temp + L.hist);
   unsigned long long *hist64 =
       wide ? reinterpret_cast<unsigned long long *>(temp + L.hist) : nullptr;
@@ -1078,6 +1086,8 @@ onesweep_status_t onesweep_binning_pass(void *d_temp, size_t *temp_bytes,
     return fail(ONESWEEP_ERROR_INVALID_VALUE, "digit bits [%d, %d) invalid", shift,
                 shift + width);
   if (n >= kMaxN) return fail(ONESWEEP_ERROR_TOO_LARGE, "n = %zu is not below 2^30", n);
+  if (n * static_cast<size_t>(key_bits / 8) > kBufferBytes)
+    return fail(ONESWEEP_ERROR_TOO_LARGE, "n = %zu %d-bit keys pass 4 GiB", n, key_bits);
   const bool has_values = d_src_vals != nullptr || d_dst_vals != nullptr;
   Resolved rc;
   onesweep_status_t st;

@@ -47,11 +47,13 @@ namespace onesweep {
 //    read-then-write per batch.
 enum RankAlgorithm : int { kRankBallot = 0, kRankPresence = 1, kRankAtomic = 2 };
 
-// Drop any global store whose index is not below n. Consistent counts never
-// produce such an index; the check only turns a logic error into a wrong
-// result instead of a memory fault.
+// Every tile checks, once, that each digit's destination run lies inside the
+// output (a look-back that gave up or inconsistent counts could place it
+// elsewhere); a tile that fails writes nothing and sets bit 1 of the error
+// word. With correct ranking that bounds every store. This switch adds a check
+// of every single store index against n on top (debugging of the ranking).
 #ifndef ONESWEEP_CHECKED_STORES
-#define ONESWEEP_CHECKED_STORES 1
+#define ONESWEEP_CHECKED_STORES 0
 #endif
 constexpr bool kCheckedStores = ONESWEEP_CHECKED_STORES != 0;
 
@@ -159,6 +161,47 @@ constexpr int binning_waves_per_eu() {
 // kOrdered: keys are ranked by their ordered bits (signed, floating-point or
 // descending order); false for unsigned ascending sorts. Idx: type of element
 // positions (uint64_t for sorts of 2^31 elements or more).
+// Element-indexed buffer stores: the memory unit forms the address from the
+// base and the index times the element size, so a store takes one 32-bit
+// index and no vector address arithmetic, and drops an index at or past the
+// record count (the output's length). The unit's offset is 32 bits wide, so
+// they serve outputs of at most 4 GiB. Word 3 of the resource: 32-bit data
+// format, the value every gfx9-family buffer resource takes.
+__device__ void buffer_store_i32(int32_t v, __amdgpu_buffer_rsrc_t r, int32_t index,
+                                 int32_t voffset, int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.store.i32");
+__device__ void buffer_store_i64(int64_t v, __amdgpu_buffer_rsrc_t r, int32_t index,
+                                 int32_t voffset, int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.store.i64");
+constexpr int kRsrcWord3 = 0x00020000;
+
+// Stores of one output array: through an element-indexed buffer resource
+// (kBuffered: outputs of at most 4 GiB), else plain stores (optionally
+// checked). The choice is made per kernel: chosen per store, its scalar
+// branches cost about 1% of a pass, and compiling the scatter twice in one
+// kernel spills registers.
+template <typename T, typename Idx, bool kBuffered>
+struct ElementStore {
+  T *base;
+  Idx n;
+  __amdgpu_buffer_rsrc_t rsrc;
+  __device__ __forceinline__ ElementStore(T *p, Idx count) : base(p), n(count) {
+    if constexpr (kBuffered)
+      rsrc = __builtin_amdgcn_make_buffer_rsrc(p, static_cast<short>(sizeof(T)),
+                                               static_cast<int>(count), kRsrcWord3);
+  }
+  __device__ __forceinline__ void put(Idx i, T v) const {
+    if constexpr (kBuffered) {
+      if constexpr (sizeof(T) == 4)
+        buffer_store_i32(static_cast<int32_t>(v), rsrc, static_cast<int32_t>(i), 0, 0, 0);
+      else
+        buffer_store_i64(static_cast<int64_t>(v), rsrc, static_cast<int32_t>(i), 0, 0, 0);
+    } else if (!kCheckedStores || i < n) {
+      base[i] = v;
+    }
+  }
+};
+
 template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode, bool kOrdered,
           typename Idx>
 __global__ void __launch_bounds__(kBlock)
@@ -200,6 +243,10 @@ __global__ void __launch_bounds__(kBlock)
   // pass, 2^27 pairs 822 -> 774 us; the second round trip costs nothing
   // measurable at equal tiles (548 against 547 us at 1024 x 9).
   constexpr bool kSplit = sizeof(K) == 8;
+  // Buffer stores: kernels with 32-bit positions, whose outputs the host
+  // keeps within 4 GiB (larger sorts take 64-bit positions); the segmented
+  // 64-bit kernels, whose keys may pass 4 GiB, store plainly.
+  constexpr bool kBuffered = sizeof(Idx) == 4 && !(kSeg && sizeof(K) == 8);
   constexpr size_t kKeyBytes = (kSplit ? 4 : sizeof(K)) * kTile;
   constexpr size_t kRankBytes = sizeof(uint32_t) * kWaves * kRadix * kEntryWords;
   constexpr size_t kTileBytes = kKeyBytes > kRankBytes ? kKeyBytes : kRankBytes;
@@ -211,6 +258,7 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ uint32_t s_wave_sum[kRadix / kWave];
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_uniform;  // 1 + the tile's only digit, or 0
+  __shared__ uint32_t s_outside;  // 1: a destination run leaves the output
   __shared__ uint32_t s_seg_sum[kRadix / kWave];  // segmented: digit counts per wave
 
   uint32_t *s_rank = reinterpret_cast<uint32_t *>(s_stage);
@@ -255,6 +303,7 @@ __global__ void __launch_bounds__(kBlock)
     // concurrent tiles writing far-apart parts of each bin.
     s_tile = atomicAdd(a.tile_counter, 1u);
     s_uniform = 0u;
+    s_outside = 0u;
   }
   __syncthreads();
   uint32_t tile = s_tile + a.tile_first;  // tickets count from the strip's start
@@ -333,7 +382,7 @@ __global__ void __launch_bounds__(kBlock)
         if (total == len) break;
         if (++rounds >= a.spin_limit) {  // bounded wait: give up, record it
           if (tid == 0)
-            __hip_atomic_store(a.lookback_error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(a.lookback_error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
         __builtin_amdgcn_s_sleep(2);
@@ -607,7 +656,7 @@ __global__ void __launch_bounds__(kBlock)
         }
         if (found) break;
         if (++rounds >= a.spin_limit) {  // bounded wait: give up, record it
-          __hip_atomic_store(a.lookback_error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_or(a.lookback_error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
         pred -= consumed;
@@ -617,14 +666,26 @@ __global__ void __launch_bounds__(kBlock)
                    kFlagG | (exclusive + published));
     }
     // Global position of the key at tile position q with digit v is
-    // s_gbase[v] + q (unsigned wrap-around cancels in the sum).
-    s_gbase[tid] = bin_start + exclusive - local_start;
+    // s_gbase[v] + q (unsigned wrap-around cancels in the sum). The run of
+    // the tile's keys of digit v must lie in the output, and a correct run
+    // never starts below the digit's tile position; a tile that fails either
+    // writes nothing, as does every tile of a buffered kernel handed an
+    // output over 4 GiB.
+    const Idx run = bin_start + exclusive;
+    const bool too_big = kBuffered && static_cast<uint64_t>(n) * sizeof(K) > (uint64_t{1} << 32);
+    if (too_big || (published != 0u && (run < local_start || run > n || n - run < published))) {
+      s_outside = 1u;
+      __hip_atomic_fetch_or(a.lookback_error, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_gbase[tid] = run - local_start;
     // The strip's last tile hands the next strip its bin starts.
     if constexpr (kMode == kBinChained)
       if (a.next_bin_offsets != nullptr && tile + 1u == a.tile_first + gridDim.x)
         a.next_bin_offsets[tid] = bin_start + exclusive + published;
   }
   __syncthreads();
+  if (s_outside != 0u) return;  // recorded above; nothing is written
+  const ElementStore<K, Idx, kBuffered> out(dst, n);
 
   // 5b'. Short-circuit: every key of a one-digit tile goes to its bin at its
   // input position, straight from registers.
@@ -632,17 +693,11 @@ __global__ void __launch_bounds__(kBlock)
     if constexpr (kLateVals) load_vals();
     const Idx g0 = s_gbase[uniform - 1u] + static_cast<uint32_t>(wave * kWaveItems + lane);
 #pragma unroll
-    for (int i = 0; i < kIpt; ++i) {
-      const Idx g = g0 + static_cast<uint32_t>(i * kWave);
-      if (!kCheckedStores || g < n) dst[g] = key[i];
-    }
+    for (int i = 0; i < kIpt; ++i) out.put(g0 + static_cast<uint32_t>(i * kWave), key[i]);
     if constexpr (kVals) {
-      uint32_t *__restrict__ vdst = a.vals[dst_id];
+      const ElementStore<uint32_t, Idx, kBuffered> vout(a.vals[dst_id], n);
 #pragma unroll
-      for (int i = 0; i < kIpt; ++i) {
-        const Idx g = g0 + static_cast<uint32_t>(i * kWave);
-        if (!kCheckedStores || g < n) vdst[g] = val[i];
-      }
+      for (int i = 0; i < kIpt; ++i) vout.put(g0 + static_cast<uint32_t>(i * kWave), val[i]);
     }
     return;
   }
@@ -675,18 +730,15 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) g[i] = s_gbase[digit(k[i])] + static_cast<uint32_t>(i * kBlock + tid);
 #pragma unroll
-    for (int i = 0; i < kIpt; ++i) {
-      if (!kCheckedStores || g[i] < n) dst[g[i]] = k[i];
-      if constexpr (kVals) dst_idx[i] = g[i];
-    }
+    for (int i = 0; i < kIpt; ++i) out.put(g[i], k[i]);
   } else {
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t q = i * kBlock + tid;
-      if (q < tile_count) {
+      if (full || q < tile_count) {
         const K k = slot_key(i, q);
         const Idx g = s_gbase[digit(k)] + q;
-        if (!kCheckedStores || g < n) dst[g] = k;
+        out.put(g, k);
         if constexpr (kVals) dst_idx[i] = g;
       }
     }
@@ -694,7 +746,7 @@ __global__ void __launch_bounds__(kBlock)
 
   // 5c. Values follow their keys through the same LDS positions.
   if constexpr (kVals) {
-    uint32_t *__restrict__ vdst = a.vals[dst_id];
+    const ElementStore<uint32_t, Idx, kBuffered> vout(a.vals[dst_id], n);
     if constexpr (kLateVals) load_vals();
     __syncthreads();
 #pragma unroll
@@ -703,8 +755,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < kIpt; ++i) {
       const uint32_t q = i * kBlock + tid;
-      if ((full || q < tile_count) && (!kCheckedStores || dst_idx[i] < n))
-        vdst[dst_idx[i]] = s_vals[q];
+      if (full || q < tile_count) vout.put(dst_idx[i], s_vals[q]);
     }
   }
 }
@@ -869,6 +920,7 @@ __global__ void __launch_bounds__(kBlock)
 #define ONESWEEP_WIDE_SHAPES(X)   \
   X(uint32_t, false, 1024, 19, 0) \
   X(uint32_t, true, 1024, 16, 0)  \
+  X(uint32_t, true, 1024, 19, 0)  \
   X(uint64_t, false, 1024, 14, 0) \
   X(uint64_t, true, 1024, 14, 0)
 
@@ -909,9 +961,10 @@ size_t binning_tile_items(const BinningShape &s) {
 // 1024 x 16 or 1024 x 11, 4% faster than 1024 x 11 alone), 1024 x 19 from
 // 2^23 (2^28: 2.45 against 2.58 with 1024 x 16 and 2.95 with 1024 x 11).
 // 32-bit pairs: 1024 x 11 from 2^21 (the sweep: 8% faster than 1024 x 8
-// between 2^21 and 2^22), 1024 x 16 from 2^22 (2^26: 1.23 against 1.29 with
-// 1024 x 11 and 1.27 with 1024 x 18; at 2^28 a pass takes 1086 us, as with
-// 1024 x 18, which spills a few registers). 64-bit keys and pairs,
+// between 2^21 and 2^22), 1024 x 16 from 2^22 (2^24: 0.329 against 0.332
+// with 1024 x 19), 1024 x 19 from 2^26 (2^26: 1.150 against 1.171 with
+// 1024 x 16; 2^28: 4.53 against 4.61; it fits 64 registers since the stores
+// go through buffer resources). 64-bit keys and pairs,
 // regrouped in two 32-bit halves: 1024 x 9 from 2^21 (64-bit pairs: 1-2%
 // faster than 1024 x 8 in the seeded sweep), 1024 x 12 from 2^22 and
 // 1024 x 14 from 2^26 (2^27 keys: 4.36 ms against 4.41 with 1024 x 12 and
@@ -929,7 +982,8 @@ BinningShape binning_default_shape(int key_bits, bool has_values, size_t n) {
   if (n < (size_t(1) << 21)) return BinningShape{32, has_values, 1024, 8, kRankBallot};
   if (has_values) {
     if (n < (size_t(1) << 22)) return BinningShape{32, true, 1024, 11, kRankBallot};
-    return BinningShape{32, true, 1024, 16, kRankBallot};
+    if (n < (size_t(1) << 26)) return BinningShape{32, true, 1024, 16, kRankBallot};
+    return BinningShape{32, true, 1024, 19, kRankBallot};
   }
   if (n < (size_t(3) << 20)) return BinningShape{32, false, 1024, 11, kRankBallot};
   if (n < (size_t(1) << 23)) return BinningShape{32, false, 1024, 16, kRankBallot};

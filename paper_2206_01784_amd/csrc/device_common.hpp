@@ -49,7 +49,7 @@ struct PassPlan {
   uint32_t dst[kMaxPlaces];
   uint32_t copy_src;  // buffer copied into the output at the end, or kNoBuffer
   uint32_t executed;
-  uint32_t lookback_error;  // set to 1 by a binning pass whose look-back gave up
+  uint32_t lookback_error;  // bit 0: a look-back gave up; bit 1: a run fell outside
   uint32_t pad[13];
 };
 static_assert(sizeof(PassPlan) <= 256, "plan fits one 256-byte slot");
@@ -67,7 +67,7 @@ struct SegmentPlan {
   uint32_t error;                      // 1: offsets invalid, nothing is sorted
   uint32_t count[kSegClasses + 1];     // segments per class (last: large)
   uint32_t large_tiles;                // binning tiles of all large segments
-  uint32_t lookback_error;             // set to 1 by a binning pass whose look-back gave up
+  uint32_t lookback_error;             // bit 0: a wait gave up; bit 1: a run fell outside
   uint32_t pad[57];
 };
 static_assert(sizeof(SegmentPlan) == 256, "one 256-byte slot");
@@ -107,7 +107,7 @@ struct BinningArgs {
   Idx *next_bin_offsets;
   // Bounded look-back wait: a tile that has polled its window of
   // predecessors spin_limit times without reaching an inclusive prefix gives
-  // up, sets *lookback_error to 1 and carries on with what it has summed (its
+  // up, sets bit 0 of *lookback_error and carries on with what it has summed (its
   // output is then wrong, but every workgroup exits). Legitimate look-backs
   // take a few polls; the default limit is seconds of waiting.
   uint32_t *lookback_error;

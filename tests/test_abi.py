@@ -153,10 +153,11 @@ def test_key_type_and_direction_validation_needs_no_gpu():
 
 def test_strip_configuration_and_size_limits_need_no_gpu():
     """Whole plain sorts accept n below 2^36 (strips of at most 2^29 keys per
-    chained scan; from 2^31 keys on, 64-bit counts, bin starts and positions,
-    built for the default large-input tile shapes only, and no
-    reduce-then-scan); the single-pass, histogram and segmented entry points
-    keep one chained scan and the 2^30 limit."""
+    chained scan; from 2^31 keys, or more than 4 GiB of keys, on, 64-bit
+    counts, bin starts and positions, built for the default large-input tile
+    shapes only, and no reduce-then-scan); the single-pass, histogram and
+    segmented entry points keep one chained scan and the 2^30 limit, and the
+    single pass also at most 4 GiB of keys."""
     import paper_2206_01784_amd as ow
     lib = ow.library()
     size = ctypes.c_size_t(0)
@@ -175,19 +176,26 @@ def test_strip_configuration_and_size_limits_need_no_gpu():
         assert rc == ow.ERROR_INVALID_VALUE, bad
     assert lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 1 << 36, 32, 0, 32, 1,
                                   None, None) == ow.ERROR_TOO_LARGE
-    # 2^31 keys: 64-bit counts and bin offsets (8 bytes per entry), five strips
-    wide = ow.sort_temp_bytes(1 << 31, 32)
-    narrow = ow.sort_temp_bytes((1 << 31) - 1, 32)
-    assert wide - narrow >= 2 * 8 * 256 * 4 - 8 * 256 * 4
+    # beyond 4 GiB of keys: 64-bit counts and bin offsets (8 bytes per entry)
+    wide = ow.sort_temp_bytes((1 << 30) + 1, 32)
+    narrow = ow.sort_temp_bytes(1 << 30, 32)
+    assert wide - narrow >= 8 * 256 * 4
     assert ow.sort_temp_bytes(1 << 31, 64, True) >= 12 * (1 << 31)
     for kb, vals in ((32, False), (32, True), (64, False), (64, True)):
         assert ow.tile_items(kb, vals, None, 1 << 31) > 0
-    for cfg in (ow.make_config(1024, 8), ow.make_config(algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)):
-        rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, 1 << 31, 32, 0, 32, 1,
-                                    ctypes.byref(cfg), None)
-        assert rc == ow.ERROR_UNSUPPORTED
-        assert lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, (1 << 31) - 1, 32, 0,
-                                      32, 1, ctypes.byref(cfg), None) == 0
+    for kb, last in ((32, 1 << 30), (64, 1 << 29)):
+        for cfg in (ow.make_config(1024, 8),
+                    ow.make_config(algorithm=ow.ALGORITHM_REDUCE_THEN_SCAN)):
+            rc = lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, last + 1, kb, 0,
+                                        kb, 1, ctypes.byref(cfg), None)
+            assert rc == ow.ERROR_UNSUPPORTED, (kb, last)
+            assert lib.onesweep_sort_keys(None, ctypes.byref(size), None, None, last, kb, 0,
+                                          kb, 1, ctypes.byref(cfg), None) == 0, (kb, last)
+    assert lib.onesweep_binning_pass(None, ctypes.byref(size), None, None, None, None,
+                                     (1 << 29) + 1, 64, 0, 8, None, None,
+                                     None) == ow.ERROR_TOO_LARGE
+    assert lib.onesweep_binning_pass(None, ctypes.byref(size), None, None, None, None, 1 << 29,
+                                     64, 0, 8, None, None, None) == 0
     assert lib.onesweep_sort_segments(None, ctypes.byref(size), None, None, None, None, 1 << 30,
                                       None, 1, 32, 0, 32, 1, None,
                                       None) == ow.ERROR_TOO_LARGE

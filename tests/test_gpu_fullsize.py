@@ -115,7 +115,8 @@ def test_full_keys_beyond_2p30(ow):
     """2^30 + 4097 uint32 keys: with the default 1024 x 19 tiles and strips of
     at most 2^29 keys, each binning pass runs three strips (27,594 + 27,594
     tiles and a last one-tile strip), each its own chained scan, the bin
-    starts carried from strip to strip; bit-exact against the oracle."""
+    starts carried from strip to strip; more than 4 GiB of keys, so 64-bit
+    counts and positions; bit-exact against the oracle."""
     n = (1 << 30) + 4097
     print(f"[full] 2^30 + 4097 u32 keys, n={n}", flush=True)
     keys = W.uniform(91, n)

@@ -156,10 +156,45 @@ def test_lookback_wait_is_bounded(ow):
     dk, _, temp = ow.binning_pass(d_keys, d_off, 0, 8,
                                   config=ow.make_config(lookback_spin_limit=1))
     torch.cuda.synchronize()
-    assert int(host(temp[4:8].view(torch.uint32))[0]) == 1
+    assert int(host(temp[4:8].view(torch.uint32))[0]) & 1 == 1
     bad = ow.make_config(lookback_spin_limit=-1)
     with pytest.raises(ow.OnesweepError):
         ow.binning_pass(d_keys, d_off, 0, 8, config=bad)
+
+
+def test_destination_runs_outside_the_output_write_nothing(ow):
+    """Every tile checks once that the run of each of its digits lies inside
+    the output. Bin starts moved 1000 places up (forced from the host) push
+    the last runs of the top digit past the end: those tiles write nothing and
+    set bit 1 of the error word; every other tile writes its keys (and values)
+    1000 places above their places, and the first 1000 positions stay as
+    they were."""
+    n = (1 << 20) + 4097
+    keys = W.uniform(78, n)
+    vals = np.arange(n, dtype=np.uint32)
+    hist = oracle.histograms(keys, 0, 8, 8)[0]
+    off = oracle.exclusive_sums(hist[None, :])[0]
+    want_k, want_v = oracle.binning_pass(keys, 0, 8, off.astype(np.uint64), vals)
+    moved = dev((off + 1000).astype(np.uint32))
+    d_keys, d_vals = dev(keys), dev(vals)
+    for with_vals in (False, True):
+        print(f"[outside] values={with_vals}", flush=True)
+        dk = torch.full((n,), -1, dtype=torch.int32, device="cuda").view(torch.uint32)
+        dv = torch.full((n,), -1, dtype=torch.int32, device="cuda").view(torch.uint32)
+        _, _, temp = ow.binning_pass(d_keys, moved, 0, 8, dst=dk,
+                                     src_values=d_vals if with_vals else None,
+                                     dst_values=dv if with_vals else None)
+        torch.cuda.synchronize()
+        assert int(host(temp[4:8].view(torch.uint32))[0]) & 2 == 2
+        got_k = host(dk)
+        assert np.all(got_k[:1000] == np.uint32(0xFFFFFFFF))
+        written = got_k[1000:] != np.uint32(0xFFFFFFFF)
+        assert 0 < np.count_nonzero(~written) < n // 2
+        assert np.array_equal(got_k[1000:][written], want_k[:n - 1000][written])
+        if with_vals:
+            got_v = host(dv)
+            assert np.all(got_v[:1000] == np.uint32(0xFFFFFFFF))
+            assert np.array_equal(got_v[1000:][written], want_v[:n - 1000][written])
 
 
 # ------------------------------------------------------------------ whole sorts
