@@ -328,7 +328,7 @@ onesweep_status_t onesweep_sort_segments(void *d_temp, size_t *temp_bytes,
  * Autotuner of the segmented sort (not in the paper): times
  * onesweep_sort_segments on the caller's data for every built tile shape of
  * the segmented path (32-bit keys: 256x8, 256x16, 512x16, 1024x8, 1024x11,
- * 1024x16;
+ * 1024x16, 1024x19;
  * 64-bit keys: 256x8, 256x16, 512x8, 1024x8, 1024x9, 1024x14) crossed with seven
  * settings of the segment class limits and with 8- and 7-bit digits (7 only
  * where the bit range makes at most 8 places)

@@ -1192,8 +1192,8 @@ onesweep_status_t onesweep_tune_segments(void *d_temp, size_t *temp_bytes,
   // Candidates: every tile shape built for the segmented path, crossed with
   // class limits that move segments between the LDS classes and the tile
   // path.
-  static const int kShapes32[][2] = {{256, 8},  {256, 16},  {512, 16},
-                                     {1024, 8}, {1024, 11}, {1024, 16}};
+  static const int kShapes32[][2] = {{256, 8},  {256, 16},  {512, 16}, {1024, 8},
+                                     {1024, 11}, {1024, 16}, {1024, 19}};
   static const int kShapes64[][2] = {{256, 8},  {256, 16}, {512, 8},
                                      {1024, 8}, {1024, 9}, {1024, 14}};
   static const int kLimits[][3] = {{0, 0, 0},   {0, 0, 4096},  {0, 0, 2048}, {0, 0, -1},

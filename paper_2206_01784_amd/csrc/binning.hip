@@ -880,6 +880,8 @@ __global__ void __launch_bounds__(kBlock)
   X(uint32_t, true, 1024, 11, 0)           \
   X(uint32_t, false, 1024, 16, 0)          \
   X(uint32_t, true, 1024, 16, 0)           \
+  X(uint32_t, false, 1024, 19, 0)          \
+  X(uint32_t, true, 1024, 19, 0)           \
   X(uint64_t, false, 1024, 9, 0)           \
   X(uint64_t, true, 1024, 9, 0)            \
   X(uint64_t, false, 1024, 14, 0)          \

@@ -133,7 +133,7 @@ def test_segments_one_stream_and_two_streams_agree(ow, kb):
 @pytest.mark.parametrize("limits", LIMITS)
 @pytest.mark.parametrize("kb,shape", [(32, (256, 8)), (32, (256, 16)), (32, (512, 16)),
                                       (32, (1024, 8)), (32, (1024, 11)), (32, (1024, 16)),
-                                      (64, (256, 8)), (64, (512, 8)), (64, (256, 16)),
+                                      (32, (1024, 19)), (64, (256, 8)), (64, (512, 8)), (64, (256, 16)),
                                       (64, (1024, 9)), (64, (1024, 14))])
 def test_segments_class_limits_and_tiles(ow, limits, kb, shape):
     cfg = ow.make_config(block_threads=shape[0], items_per_thread=shape[1],
@@ -333,7 +333,8 @@ def test_segments_tuner_picks_a_built_config_and_sorts(ow):
     assert np.array_equal(host(ko), want_k)
     assert np.array_equal(host(vo), want_v)
     assert (cfg.block_threads, cfg.items_per_thread) in [(256, 8), (256, 16), (512, 16),
-                                                         (1024, 8), (1024, 11), (1024, 16)]
+                                                         (1024, 8), (1024, 11), (1024, 16),
+                                                         (1024, 19)]
     # the chosen config sorts the same data bit-exactly again
     k2, v2 = ow.sort_segments(tk, to, tv, config=cfg)
     torch.cuda.synchronize()
