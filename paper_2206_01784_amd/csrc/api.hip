@@ -49,7 +49,7 @@ constexpr size_t kWideN = size_t(1) << 31;
 constexpr size_t kMaxSortN = size_t(1) << 36;
 // The 32-bit-position binning kernels store through buffer resources, whose
 // offsets are 32-bit: a sort whose key output passes 4 GiB (32-bit keys from
-// 2^30 on, 64-bit keys from 2^29) takes the 64-bit-position path too.
+// 2^30 + 1 on, 64-bit keys from 2^29 + 1) takes the 64-bit-position path too.
 constexpr size_t kBufferBytes = size_t(1) << 32;
 inline bool wide_positions(size_t n, int key_bits) {
   return n >= kWideN || n * static_cast<size_t>(key_bits / 8) > kBufferBytes;

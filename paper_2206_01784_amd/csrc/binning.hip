@@ -150,17 +150,6 @@ constexpr int binning_waves_per_eu() {
   return kBlock == 1024 || (kIpt * sizeof(K)) <= 32 ? 8 : ((kIpt * sizeof(K)) <= 48 ? 6 : 4);
 }
 
-// kMode: kBinChained, one sequence with a chained scan over its tiles;
-// kBinSegmented, the tiles of the large segments of a segmented sort (each
-// segment its own chained scan; a tile turns its segment's digit counts of
-// the place into bin starts itself); kBinSegCounted, the first place of the
-// segmented sort in the same launch as the counting of every place (see
-// count_segment_tile); kBinDownsweep, the scatter step of reduce-then-scan:
-// every tile's exclusive prefix per digit is read from a table that the
-// upsweep and tile-scan kernels filled beforehand.
-// kOrdered: keys are ranked by their ordered bits (signed, floating-point or
-// descending order); false for unsigned ascending sorts. Idx: type of element
-// positions (uint64_t for sorts of 2^31 elements or more).
 // Element-indexed buffer stores: the memory unit forms the address from the
 // base and the index times the element size, so a store takes one 32-bit
 // index and no vector address arithmetic, and drops an index at or past the
@@ -202,6 +191,18 @@ struct ElementStore {
   }
 };
 
+// kMode: kBinChained, one sequence with a chained scan over its tiles;
+// kBinSegmented, the tiles of the large segments of a segmented sort (each
+// segment its own chained scan; a tile turns its segment's digit counts of
+// the place into bin starts itself); kBinSegCounted, the first place of the
+// segmented sort in the same launch as the counting of every place (see
+// count_segment_tile); kBinDownsweep, the scatter step of reduce-then-scan:
+// every tile's exclusive prefix per digit is read from a table that the
+// upsweep and tile-scan kernels filled beforehand.
+// kOrdered: keys are ranked by their ordered bits (signed, floating-point or
+// descending order); false for unsigned ascending sorts. Idx: type of element
+// positions (uint64_t for sorts of 2^31 elements or more, or of more than
+// 4 GiB of keys).
 template <typename K, bool kVals, int kBlock, int kIpt, int kRank, int kMode, bool kOrdered,
           typename Idx>
 __global__ void __launch_bounds__(kBlock)
